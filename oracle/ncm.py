@@ -1,0 +1,367 @@
+"""Oracle: neural constitutive model (kinematic layer + MICNN + CGO route).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Everything is batched over a leading axis of quadrature points and works for
+real (float64) and complex (complex128) inputs, so that complex-step
+differentiation can pin it.
+
+Readings of the paper used here
+-------------------------------
+R1  I5,ij second-order tensor for i != j (App. A.2.1): the printed
+    2 sym(a^i (x) B a^j) holds only for i = j; the derivative of
+    I5,ij = A^i . C^2 A^j pushed forward is  B M + M B  with M = sym(a^i (x) a^j).
+R2  Isochoric I5 table (App. A.2.2) uses the isochoric B~ = J^{-2/3} B and
+    a~ = J^{-1/3} a throughout (the printed G~5 shows B).
+R3  The stiffness sum over the network Hessian runs over m and n
+    (eq. stiffnes-cgo prints d2N/dK_m dK_m).
+R4  The symmetric product is the standard
+    (A [x] B)_ijkl = (A_ik B_jl + A_il B_jk)/2; the printed B_kj index is
+    equivalent for the symmetric arguments used.
+R5  I4 and I5 inputs use unordered pairs i <= j of structural vectors.
+R6  Features (extends the kinematic layer of App. C to anisotropy):
+    K = [I1~ - 3, I2~^{3/2} - 3^{3/2}, (J - 1)^2,
+         {I4~_ij - A^i.A^j}_{i<=j}, {I5~_ij - A^i.A^j}_{i<=j}],
+    all zero at F = I.
+R7  The first hidden layer has one matrix W1 (A^(1) and B^(1) multiply the same
+    z^(0) = K); hidden layers carry biases c_k; the output layer has none.
+R8  Activation: softplus F(y) = log(1 + e^y), F' = sigma(y),
+    F'' = sigma(y)(1 - sigma(y)).
+R9  Optional normalisation (energy- and stress-free reference state):
+    Psi = N(K) - N(0) - sum_{i<=j} kappa_ij K_{4,ij},
+    kappa_ij = dN/dK_{4,ij}(0) + 2 dN/dK_{5,ij}(0).
+R10 J <= 0: the isochoric factors use I3 = J^2 > 0; values are still produced.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+EYE = np.eye(3)
+S32 = 3.0 ** 1.5
+
+
+# ----------------------------------------------------------------------------
+# small tensor helpers (batched over the leading axis)
+# ----------------------------------------------------------------------------
+def _sym(A):
+    return 0.5 * (A + np.swapaxes(A, -1, -2))
+
+
+def _outer(A, B):
+    """(A (x) B)_ijkl = A_ij B_kl."""
+    return np.einsum("...ij,...kl->...ijkl", A, B)
+
+
+def _boxtimes(A, B):
+    """(A [x] B)_ijkl = (A_ik B_jl + A_il B_jk)/2   (reading R4)."""
+    return 0.5 * (np.einsum("...ik,...jl->...ijkl", A, B)
+                  + np.einsum("...il,...jk->...ijkl", A, B))
+
+
+def _det3(F):
+    return (F[..., 0, 0] * (F[..., 1, 1] * F[..., 2, 2] - F[..., 1, 2] * F[..., 2, 1])
+            - F[..., 0, 1] * (F[..., 1, 0] * F[..., 2, 2] - F[..., 1, 2] * F[..., 2, 0])
+            + F[..., 0, 2] * (F[..., 1, 0] * F[..., 2, 1] - F[..., 1, 1] * F[..., 2, 0]))
+
+
+def _inv3(F):
+    """Inverse by the adjugate (works for complex entries)."""
+    a = F
+    cof = np.empty_like(a)
+    cof[..., 0, 0] = a[..., 1, 1] * a[..., 2, 2] - a[..., 1, 2] * a[..., 2, 1]
+    cof[..., 0, 1] = -(a[..., 1, 0] * a[..., 2, 2] - a[..., 1, 2] * a[..., 2, 0])
+    cof[..., 0, 2] = a[..., 1, 0] * a[..., 2, 1] - a[..., 1, 1] * a[..., 2, 0]
+    cof[..., 1, 0] = -(a[..., 0, 1] * a[..., 2, 2] - a[..., 0, 2] * a[..., 2, 1])
+    cof[..., 1, 1] = a[..., 0, 0] * a[..., 2, 2] - a[..., 0, 2] * a[..., 2, 0]
+    cof[..., 1, 2] = -(a[..., 0, 0] * a[..., 2, 1] - a[..., 0, 1] * a[..., 2, 0])
+    cof[..., 2, 0] = a[..., 0, 1] * a[..., 1, 2] - a[..., 0, 2] * a[..., 1, 1]
+    cof[..., 2, 1] = -(a[..., 0, 0] * a[..., 1, 2] - a[..., 0, 2] * a[..., 1, 0])
+    cof[..., 2, 2] = a[..., 0, 0] * a[..., 1, 1] - a[..., 0, 1] * a[..., 1, 0]
+    det = _det3(F)
+    return np.swapaxes(cof, -1, -2) / det[..., None, None]
+
+
+def pairs(n_sv: int):
+    """Unordered pairs (i, j), i <= j, of structural vectors (reading R5)."""
+    return [(i, j) for i in range(n_sv) for j in range(i, n_sv)]
+
+
+def num_inputs(n_sv: int) -> int:
+    return 3 + 2 * len(pairs(n_sv))
+
+
+# ----------------------------------------------------------------------------
+# Kinematic layer: invariants (eq. standard-inv-I; App. A.2.1-A.2.2)
+# ----------------------------------------------------------------------------
+def invariants(F, Avec):
+    """Raw invariants.  Returns dict with I1, I2, I3, J, I4[pair], I5[pair]."""
+    C = np.einsum("...ki,...kj->...ij", F, F)
+    I1 = np.einsum("...ii->...", C)
+    C2 = np.einsum("...ij,...jk->...ik", C, C)
+    I2 = 0.5 * (I1 ** 2 - np.einsum("...ii->...", C2))
+    J = _det3(F)
+    I3 = J * J  # det C = (det F)^2
+    n_sv = Avec.shape[0]
+    I4, I5 = [], []
+    for (i, j) in pairs(n_sv):
+        I4.append(np.einsum("i,...ij,j->...", Avec[i], C, Avec[j]))
+        I5.append(np.einsum("i,...ij,j->...", Avec[i], C2, Avec[j]))
+    return dict(C=C, I1=I1, I2=I2, I3=I3, J=J, I4=I4, I5=I5)
+
+
+def features(F, Avec):
+    """Feature vector K (reading R6) from the isochoric invariants
+    I~_m = I_m I3^{alpha_m}, alpha = -1/3 for {1, (4,ij)}, -2/3 for {2, (5,ij)}."""
+    inv = invariants(F, Avec)
+    I3 = inv["I3"]
+    p13 = I3 ** (-1.0 / 3.0)
+    p23 = I3 ** (-2.0 / 3.0)
+    I1t = inv["I1"] * p13
+    I2t = inv["I2"] * p23
+    J = inv["J"]
+    feats = [I1t - 3.0, I2t ** 1.5 - S32, (J - 1.0) ** 2]
+    n_sv = Avec.shape[0]
+    prs = pairs(n_sv)
+    for k, (i, j) in enumerate(prs):
+        feats.append(inv["I4"][k] * p13 - Avec[i] @ Avec[j])
+    for k, (i, j) in enumerate(prs):
+        feats.append(inv["I5"][k] * p23 - Avec[i] @ Avec[j])
+    return np.stack(feats, axis=-1)
+
+
+def _softplus(y):
+    if np.iscomplexobj(y):
+        return np.log1p(np.exp(y))
+    return np.maximum(y, 0.0) + np.log1p(np.exp(-np.abs(y)))
+
+
+def _sigmoid(y):
+    if np.iscomplexobj(y):
+        return 1.0 / (1.0 + np.exp(-y))
+    e = np.exp(-np.abs(y))
+    return np.where(y >= 0, 1.0 / (1.0 + e), e / (1.0 + e))
+
+
+# ----------------------------------------------------------------------------
+# Inner network: (M)ICNN, one-pass value + gradient + Hessian (Alg. 4)
+# ----------------------------------------------------------------------------
+def micnn(K, hidden, a, b):
+    """Alg. 4 of App. B.2.
+
+    ``hidden`` = [(W1, None, c1), (A2, B2, c2), ...]; ``a``, ``b`` output weights.
+    K: (n, p).  Returns N (n,), dN (n, p), d2N (n, p, p).
+    """
+    n, p = K.shape
+    z = K
+    dz = np.broadcast_to(np.eye(p), (n, p, p))
+    d2z = np.zeros((n, p, p, p), dtype=K.dtype)
+    for (A, B, c) in hidden:
+        y = np.einsum("jk,nk->nj", A, z) + c
+        dy = np.einsum("jk,nkm->njm", A, dz)
+        if B is not None:
+            y = y + np.einsum("jk,nk->nj", B, K)
+            dy = dy + B[None]
+        d2y = np.einsum("jk,nkmo->njmo", A, d2z)
+        f0 = _softplus(y)
+        s = _sigmoid(y)
+        f1 = s
+        f2 = s * (1.0 - s)
+        d2z = f1[:, :, None, None] * d2y + f2[:, :, None, None] * dy[:, :, :, None] * dy[:, :, None, :]
+        dz = f1[:, :, None] * dy
+        z = f0
+    N = z @ a + K @ b
+    dN = np.einsum("j,njm->nm", a, dz) + b
+    d2N = np.einsum("j,njmo->nmo", a, d2z)
+    return N, dN, d2N
+
+
+def micnn_value(K, hidden, a, b):
+    """Plain forward pass of eq. (icnn) (value only); used to pin Alg. 4."""
+    z = K
+    for (A, B, c) in hidden:
+        y = np.einsum("jk,nk->nj", A, z) + c
+        if B is not None:
+            y = y + np.einsum("jk,nk->nj", B, K)
+        z = _softplus(y)
+    return z @ a + K @ b
+
+
+class Model:
+    """Network parameters plus structural vectors and the normalisation flag."""
+
+    def __init__(self, hidden, a, b, Avec, normalize=False):
+        self.hidden = hidden
+        self.a = np.asarray(a)
+        self.b = np.asarray(b)
+        self.Avec = np.asarray(Avec, dtype=float).reshape(-1, 3)
+        self.normalize = bool(normalize)
+        self.p = self.b.shape[0]
+        n_sv = self.Avec.shape[0]
+        assert self.p == num_inputs(n_sv)
+        self.kappa = np.zeros(len(pairs(n_sv)))
+        self.N0 = 0.0
+        if self.normalize:
+            N0, dN0, _ = micnn(np.zeros((1, self.p)), hidden, self.a, self.b)
+            npair = len(pairs(n_sv))
+            self.N0 = float(np.real(N0[0]))
+            self.kappa = np.real(dN0[0, 3:3 + npair] + 2.0 * dN0[0, 3 + npair:3 + 2 * npair])
+
+    # inner function seen by the chain rule: value, gradient, Hessian in K
+    def inner(self, K):
+        N, dN, d2N = micnn(K, self.hidden, self.a, self.b)
+        if self.normalize:
+            npair = self.kappa.shape[0]
+            N = N - self.N0 - K[:, 3:3 + npair] @ self.kappa
+            dN = dN.copy()
+            dN[:, 3:3 + npair] -= self.kappa
+        return N, dN, d2N
+
+
+def energy(F, model):
+    """Psi(F) = N(K(F)) (eq. comp-se), plus normalisation if enabled."""
+    K = features(F, model.Avec)
+    if model.normalize:
+        npair = model.kappa.shape[0]
+        return micnn_value(K, model.hidden, model.a, model.b) - model.N0 - K[:, 3:3 + npair] @ model.kappa
+    return micnn_value(K, model.hidden, model.a, model.b)
+
+
+# ----------------------------------------------------------------------------
+# CGO push-forward tensors G^m, GG^m (eqs. second-and-fourth; App. A.2)
+# ----------------------------------------------------------------------------
+def _raw_tables(Bs, a_list, prs):
+    """Standard-invariant tables of App. A.2.1 evaluated with left tensor Bs
+    and current structural vectors a_list (the isochoric versions are the same
+    tables with B~ and a~, App. A.2.2).  Returns dicts G, GG keyed by name."""
+    n = Bs.shape[0]
+    I = np.broadcast_to(EYE, Bs.shape)
+    trB = np.einsum("...ii->...", Bs)
+    B2 = np.einsum("...ij,...jk->...ik", Bs, Bs)
+    O4 = np.zeros((n, 3, 3, 3, 3), dtype=Bs.dtype)
+    G = {"1": Bs, "2": Bs * trB[:, None, None] - B2}
+    GG = {"1": O4, "2": _outer(Bs, Bs) - _boxtimes(Bs, Bs)}
+    for k, (i, j) in enumerate(prs):
+        M = _sym(np.einsum("...i,...j->...ij", a_list[i], a_list[j]))
+        G[("4", k)] = M
+        GG[("4", k)] = O4
+        G[("5", k)] = np.einsum("...ij,...jk->...ik", Bs, M) + np.einsum("...ij,...jk->...ik", M, Bs)  # R1
+        GG[("5", k)] = _boxtimes(Bs, M) + _boxtimes(M, Bs)
+    return G, GG
+
+
+def feature_tables(F, Avec):
+    """G^m and GG^m for every feature K_m (push-forward of dK_m/dC and
+    d2K_m/dCdC), built from the isochoric tables (App. A.2.2, readings R1, R2)
+    and the volumetric J table, chained through the feature transforms (R6).
+    Returns K (n,p), G (n,p,3,3), GG (n,p,3,3,3,3)."""
+    n = F.shape[0]
+    J = _det3(F)
+    I3 = J * J
+    Bfull = np.einsum("...iK,...jK->...ij", F, F)
+    Jm23 = I3 ** (-1.0 / 3.0)   # J^{-2/3}
+    Jm13 = I3 ** (-1.0 / 6.0)   # J^{-1/3}
+    Bt = Bfull * Jm23[:, None, None]
+    n_sv = Avec.shape[0]
+    prs = pairs(n_sv)
+    a_cur = [np.einsum("...iJ,J->...i", F, Avec[i]) for i in range(n_sv)]
+    at = [x * Jm13[:, None] for x in a_cur]
+    Gt, GGt = _raw_tables(Bt, at, prs)
+    I = np.broadcast_to(EYE, (n, 3, 3)).astype(F.dtype)
+    IxI = _outer(I, I)
+    IbI = _boxtimes(I, I)
+
+    inv = invariants(F, Avec)
+    Itil = {"1": inv["I1"] * Jm23, "2": inv["I2"] * Jm23 ** 2}
+    alpha = {"1": -1.0 / 3.0, "2": -2.0 / 3.0}
+    for k in range(len(prs)):
+        Itil[("4", k)] = inv["I4"][k] * Jm23
+        Itil[("5", k)] = inv["I5"][k] * Jm23 ** 2
+        alpha[("4", k)] = -1.0 / 3.0
+        alpha[("5", k)] = -2.0 / 3.0
+
+    def iso(key):
+        """G, GG of the isochoric invariant I~ (App. A.2.2)."""
+        al = alpha[key]
+        It = Itil[key][:, None, None]
+        g = Gt[key] + al * It * I
+        gg = GGt[key] + al * (_outer(I, Gt[key]) + _outer(Gt[key], I)
+                              + It[..., None, None] * (al * IxI - IbI))
+        return g, gg
+
+    Gs, GGs, Ks = [], [], []
+    # K1 = I1~ - 3
+    g, gg = iso("1")
+    Ks.append(Itil["1"] - 3.0); Gs.append(g); GGs.append(gg)
+    # K2 = I2~^{3/2} - 3^{3/2}:  f' = 1.5 I~^{1/2}, f'' = 0.75 I~^{-1/2}
+    g, gg = iso("2")
+    I2t = Itil["2"]
+    f1 = 1.5 * I2t ** 0.5
+    f2 = 0.75 * I2t ** (-0.5)
+    Ks.append(I2t ** 1.5 - S32)
+    Gs.append(f1[:, None, None] * g)
+    GGs.append(f1[:, None, None, None, None] * gg + f2[:, None, None, None, None] * _outer(g, g))
+    # K3 = (J - 1)^2 with the J table G = J/2 I, GG = J/4 (I(x)I - 2 I[x]I)
+    gJ = 0.5 * J[:, None, None] * I
+    ggJ = 0.25 * J[:, None, None, None, None] * (IxI - 2.0 * IbI)
+    f1 = 2.0 * (J - 1.0)
+    Ks.append((J - 1.0) ** 2)
+    Gs.append(f1[:, None, None] * gJ)
+    GGs.append(f1[:, None, None, None, None] * ggJ + 2.0 * _outer(gJ, gJ))
+    for kind in ("4", "5"):
+        for k, (i, j) in enumerate(prs):
+            g, gg = iso((kind, k))
+            Ks.append(Itil[(kind, k)] - Avec[i] @ Avec[j])
+            Gs.append(g)
+            GGs.append(gg)
+    return np.stack(Ks, -1), np.stack(Gs, 1), np.stack(GGs, 1)
+
+
+def stress_stiffness(F, model, inner=None):
+    """Psi, P = dPsi/dF and AA = d2Psi/dFdF (row-major F_iJ) via the paper's
+    route: Kirchhoff tau = 2 sum N_m G^m (eq. stress-cgo), spatial stiffness
+    cc = 4 sum N_mn G^m (x) G^n + 4 sum N_m GG^m (eq. stiffnes-cgo, R3), pulled
+    back with App. A.1:  P = tau F^{-T},
+    AA_iJkL = F^{-1}_Jj (cc_ijkl + delta_ik tau_jl) F^{-1}_Ll.
+
+    ``inner`` optionally replaces the network by any callable K -> (N, dN, d2N).
+    Returns dict(psi (n,), P (n,3,3), A (n,3,3,3,3), tau, cc, K, dN, d2N).
+    """
+    K, G, GG = feature_tables(F, model.Avec)
+    fn = inner if inner is not None else model.inner
+    N, dN, d2N = fn(K)
+    tau = 2.0 * np.einsum("nm,nmij->nij", dN, G)
+    GN = np.einsum("nmo,nokl->nmkl", d2N, G)
+    cc = (4.0 * np.einsum("nmij,nmkl->nijkl", G, GN)
+          + 4.0 * np.einsum("nm,nmijkl->nijkl", dN, GG))
+    Fi = _inv3(F)
+    P = np.einsum("nij,nJj->niJ", tau, Fi)
+    I = np.eye(3)
+    AA = np.einsum("nJj,nijkl,nLl->niJkL", Fi, cc + np.einsum("ik,njl->nijkl", I, tau), Fi)
+    return dict(psi=N, P=P, A=AA, tau=tau, cc=cc, K=K, dN=dN, d2N=d2N)
+
+
+def model_from_theta(theta, p, h, L, Avec, normalize=False, has_bias=True):
+    """Unpack a parameter vector (layout documented in the input generators)."""
+    theta = np.asarray(theta)
+    off = 0
+
+    def take(shape):
+        nonlocal off
+        cnt = int(np.prod(shape))
+        x = theta[off:off + cnt].reshape(shape)
+        off += cnt
+        return x
+
+    W1 = take((h, p))
+    c1 = take((h,)) if has_bias else np.zeros(h, dtype=theta.dtype)
+    hidden = [(W1, None, c1)]
+    for _ in range(2, L + 1):
+        A = take((h, h))
+        B = take((h, p))
+        c = take((h,)) if has_bias else np.zeros(h, dtype=theta.dtype)
+        hidden.append((A, B, c))
+    a = take((h,))
+    b = take((p,))
+    if off != theta.size:
+        raise ValueError("parameter vector has the wrong length")
+    return Model(hidden, a, b, Avec, normalize=normalize)
