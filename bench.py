@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path: one Newton tangent build per step.
+
+Workload (the plain-method FP64 vs FP32 mesh case): 64^3 trilinear hex8
+unit-cube mesh (262,144 elements, 2,097,152 quadrature points, 823,875
+dofs), orthotropic with structural vectors e1 and e2 (9 inputs), MICNN with
+2 hidden layers of width 32 and softplus, weights |N(0, 0.3)| and biases
+N(0, 0.3) (seed 1), normalised reference state, displacement
+u_i = 0.05 sin(pi X_i) + 0.05 sin(pi X_{i+1}) + 0.02 h U[-1, 1] (seed 0).
+
+A step is the whole path u -> F -> features -> network (value, gradient,
+Hessian) -> chain rule (P, dP/dF) -> element residual and stiffness ->
+coloured CSR assembly of r and K.  Inputs are resident on the GPU before the
+timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "bf16_corr": 2.5e15}
+HBM_PEAK = 8.0e12
+
+
+def mlp_flops_per_point(h, L, p):
+    """Alg. 4 forward mode: 2h^2 c (L-1) + 2hc + 2hpL + 4h P2 (L-1) + h P2,
+    c = 1 + p + P2 columns, P2 = p(p+1)/2."""
+    P2 = p * (p + 1) // 2
+    c = 1 + p + P2
+    return 2 * h * h * c * (L - 1) + 2 * h * c + 2 * h * p * L + 4 * h * P2 * (L - 1) + h * P2
+
+
+def kernel_bytes(name, nen, nq, p):
+    """Algorithmic HBM bytes per element for the bandwidth-bound kernels."""
+    nd = 3 * nen
+    nout = 1 + p + p * (p + 1) // 2
+    per_qp = {"features": 72 + 8 * p, "chain": 72 + 8 * nout + 72 + 648, "gather_F": 8 * 3 * nen + 72}
+    if name in per_qp:
+        return nq * per_qp[name]
+    if name == "integrate":
+        return nq * (72 + 648 + 8) + nq * nen * 3 * 8 + 8 * nd * nd + 8 * nd
+    if name == "assemble":
+        return 24 * nd * nd + 24 * nd
+    return None
+
+
+def cpu_baseline(X, conn, u, theta, p, h, L, Av, n_sample):
+    """The oracle (plain FP64 NumPy, single thread) on a contiguous sample of
+    elements: element residual/stiffness through the push-forward route and
+    COO->CSR assembly of that sample."""
+    from oracle import fe, ncm
+    om = ncm.model_from_theta(theta, p, h, L, Av, normalize=True)
+    sub = conn[:n_sample]
+    t0 = time.perf_counter()
+    dNdX, w, _ = fe.geometry(X, sub)
+    r_e, K_e, _ = fe.element_residual_stiffness(u, sub, dNdX, w, om)
+    fe.assemble(sub, r_e, K_e, X.shape[0])
+    dt = time.perf_counter() - t0
+    nq = dNdX.shape[1]
+    return {"value": n_sample * nq / dt, "unit": "qp evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_sample} elements ({n_sample * nq} points) of the same mesh, model and "
+                      f"displacement; geometry + element residual/stiffness + assembly; {dt:.1f} s; "
+                      f"NumPy single thread on {os.cpu_count()} host cores"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64, help="cubes per side of the hex8 mesh")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16", "bf16_corr"])
+    ap.add_argument("--algo", default="forward", choices=["forward", "adjoint"])
+    ap.add_argument("--variants", default="fp32,bf16,bf16_corr",
+                    help="other precisions timed after the headline run ('' for none)")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="elements in the oracle CPU sample (0: skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_00884_amd import api, synth
+    from paper_2510_00884_amd import _lib as L
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    n = args.n
+    n_sv, h, Lh = 2, 32, 2
+    p = synth.num_inputs(n_sv)
+    X, conn, par = synth.hex_mesh(n)
+    u = synth.displacement_modes(X, 1.0 / n, seed=0)
+    theta = synth.micnn_params(p, h, Lh, seed=1)
+    Av = synth.structural_vectors(n_sv)
+    t_setup = time.perf_counter()
+    model = api.Model(theta, n_sv, h, Lh, A=Av, normalize=True, algorithm=args.algo)
+    mesh = api.FEMesh(X, conn, colour=par)
+    ut = torch.tensor(u, device="cuda").reshape(-1).contiguous()
+    ws = torch.empty(mesh.workspace_bytes(model), dtype=torch.uint8, device="cuda")
+    bufs = {}
+    api.tangent_build(model, mesh, ut, prec=args.prec, workspace=ws, bufs=bufs)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print(f"[bench] setup {t_setup:.1f} s: {mesh.n_el} elements, {mesh.n_el * mesh.nq} points, "
+          f"{3 * mesh.n_nodes} dofs, {mesh.nnz} nonzeros, {mesh.n_colours} colours", file=sys.stderr, flush=True)
+
+    lib = L.load()
+
+    def run(prec, steps, warmup, profile):
+        for _ in range(warmup):
+            api.tangent_build(model, mesh, ut, prec=prec, workspace=ws, bufs=bufs)
+        torch.cuda.synchronize()
+        if profile:
+            lib.pa_profile_enable(1)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            api.tangent_build(model, mesh, ut, prec=prec, workspace=ws, bufs=bufs)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        kern = {}
+        if profile:
+            lib.pa_profile_enable(0)
+            import ctypes as C
+            cnt = lib.pa_profile_count()
+            for i in range(cnt):
+                nm = C.c_char_p()
+                t = C.c_double()
+                k = C.c_int64()
+                lib.pa_profile_get(i, C.byref(nm), C.byref(t), C.byref(k))
+                kern[nm.value.decode()] = {"ms_total": t.value, "launches": k.value,
+                                           "ms_per_launch": t.value / max(k.value, 1)}
+        return ms, kern
+
+    ms, kern = run(args.prec, args.steps, args.warmup, True)
+    n_qp = mesh.n_el * mesh.nq
+    r_ref = bufs["r"].clone()
+    v_ref = bufs["vals"].clone()
+    print(f"[bench] {args.prec}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # dominant kernel and its roofline
+    dom = max(kern, key=lambda k: kern[k]["ms_total"]) if kern else None
+    roof = None
+    if dom:
+        per_launch_s = kern[dom]["ms_per_launch"] / 1e3
+        if dom.startswith("mlp"):
+            fl = mlp_flops_per_point(h, Lh, p) * n_qp
+            ach = fl / per_launch_s
+            roof = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[args.prec] / 1e12, "unit": "TFLOP/s",
+                    "frac": ach / PEAK[args.prec], "traffic": None, "kernel": dom,
+                    "algorithmic_per_launch": f"{mlp_flops_per_point(h, Lh, p)} FLOP/point x {n_qp} points"}
+        else:
+            launches_per_step = kern[dom]["launches"] / args.steps
+            b = kernel_bytes(dom, mesh.nen, mesh.nq, p) * mesh.n_el / launches_per_step
+            ach = b / per_launch_s
+            roof = {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK, "traffic": None, "kernel": dom}
+
+    variants = {}
+    for vp in [x for x in args.variants.split(",") if x and x != args.prec]:
+        vms, vk = run(vp, max(args.steps // 2, 2), 1, True)
+        err_r = (bufs["r"] - r_ref).norm().item() / r_ref.norm().item()
+        err_K = (bufs["vals"] - v_ref).norm().item() / v_ref.norm().item()
+        mk = next((k for k in vk if k.startswith("mlp")), None)
+        variants[vp] = {"value": n_qp / (vms / 1e3), "ms_per_step": vms,
+                        "rel_err_vs_fp64_r": err_r, "rel_err_vs_fp64_K": err_K,
+                        "mlp_ms": vk[mk]["ms_per_launch"] if mk else None,
+                        "mlp_tflops": (mlp_flops_per_point(h, Lh, p) * n_qp / (vk[mk]["ms_per_launch"] / 1e3) / 1e12) if mk else None}
+        print(f"[bench] {vp}: {vms:.3f} ms/step, err r {err_r:.2e} K {err_K:.2e}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = cpu_baseline(X, conn, u, theta, p, h, Lh, Av, min(args.cpu_sample, mesh.n_el))
+        print(f"[bench] cpu oracle: {cpu['value']:.3e} qp/s ({cpu['sample']})", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "qp evals/s (Psi+P+tangent) & elements assembled/s, FP64 vs FP32/BF16 at stated error",
+        "value": n_qp / (ms / 1e3),
+        "unit": "qp evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "bf16_corr": "bf16+f32"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": f"hex8 {n}^3 unit cube, orthotropic e1/e2 (9 inputs), MICNN 2x32 softplus, "
+                               "one Newton tangent build: residual + tangent + coloured CSR assembly",
+                   "elements": mesh.n_el, "points": n_qp, "dofs": 3 * mesh.n_nodes, "nnz": mesh.nnz,
+                   "colours": mesh.n_colours, "precision": args.prec, "algorithm": args.algo},
+        "elements_per_s": mesh.n_el / (ms / 1e3),
+        "kernels": kern,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

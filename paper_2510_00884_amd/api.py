@@ -1,0 +1,250 @@
+"""Thin PyTorch binding of the C ABI (argument marshalling only).
+
+Tensors carry device memory; every computation runs in the HIP kernels of
+libpa.so on the caller's current stream.  Names follow the C entry points
+without the ``pa_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+__all__ = ["Model", "FEMesh", "invariants", "energy_stress_tangent", "element_residual_stiffness",
+           "assemble_csr", "tangent_build", "param_backward", "num_params", "num_inputs"]
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _desc(n_sv, width, n_hidden, A=None, normalize=False, has_bias=True, algorithm="forward"):
+    d = L.ModelDesc()
+    d.n_sv = int(n_sv)
+    if A is not None:
+        A = np.asarray(A, dtype=np.float64).reshape(-1, 3)
+        for i in range(min(2, A.shape[0])):
+            for j in range(3):
+                d.A[i][j] = float(A[i, j])
+    d.n_hidden = int(n_hidden)
+    d.width = int(width)
+    d.activation = L.PA_ACT_SOFTPLUS
+    d.normalize = int(bool(normalize))
+    d.has_bias = int(bool(has_bias))
+    d.algorithm = L.ALGORITHMS[algorithm] if isinstance(algorithm, str) else int(algorithm)
+    return d
+
+
+def num_inputs(n_sv: int) -> int:
+    lib = L.load()
+    return lib.pa_num_inputs(C.byref(_desc(n_sv, 16, 2)))
+
+
+def num_params(n_sv: int, width: int, n_hidden: int, has_bias: bool = True) -> int:
+    lib = L.load()
+    return lib.pa_num_params(C.byref(_desc(n_sv, width, n_hidden, has_bias=has_bias)))
+
+
+def _prec(prec):
+    return L.PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+
+
+class Model:
+    """A neural constitutive model resident on the GPU (parameters prepared
+    once by ``pa_prepare_params``)."""
+
+    def __init__(self, theta, n_sv, width, n_hidden, A=None, normalize=False, has_bias=True,
+                 algorithm="forward", device="cuda"):
+        self.lib = L.load()
+        self.desc = _desc(n_sv, width, n_hidden, A, normalize, has_bias, algorithm)
+        self.n_sv, self.width, self.n_hidden = int(n_sv), int(width), int(n_hidden)
+        self.p = self.lib.pa_num_inputs(C.byref(self.desc))
+        self.n_params = self.lib.pa_num_params(C.byref(self.desc))
+        if not self.lib.pa_supported(C.byref(self.desc)):
+            raise L.PaError(f"unsupported model: {self.lib.pa_last_error().decode()}")
+        self.device = torch.device(device)
+        self.set_params(theta)
+
+    def set_params(self, theta):
+        th = torch.as_tensor(theta, dtype=torch.float64, device=self.device).contiguous().reshape(-1)
+        if th.numel() != self.n_params:
+            raise ValueError(f"theta has {th.numel()} entries, model needs {self.n_params}")
+        self.theta = th
+        nb = self.lib.pa_prepared_bytes(C.byref(self.desc))
+        self.prepared = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        L.check(self.lib.pa_prepare_params(C.byref(self.desc), _p(self.theta), _p(self.prepared), _stream()),
+                "pa_prepare_params")
+
+    @property
+    def algorithm(self):
+        return self.desc.algorithm
+
+    @algorithm.setter
+    def algorithm(self, a):
+        self.desc.algorithm = L.ALGORITHMS[a] if isinstance(a, str) else int(a)
+
+
+def _soa9(F):
+    """(n, 3, 3) or (n, 9) -> contiguous (9, n); (9, n) passes through."""
+    if F.dim() == 3:
+        return F.reshape(F.shape[0], 9).t().contiguous()
+    if F.dim() == 2 and F.shape[0] == 9 and F.shape[1] != 9:
+        return F.contiguous()
+    return F.reshape(-1, 9).t().contiguous()
+
+
+def invariants(model: Model, F, soa: bool = False):
+    """I_raw (4 + 2 npair, n), K (p, n), dKdF (p, 9, n)."""
+    Fs = F if soa else _soa9(F)
+    n = Fs.shape[1]
+    npair = model.n_sv * (model.n_sv + 1) // 2
+    I_raw = torch.empty((4 + 2 * npair, n), dtype=torch.float64, device=Fs.device)
+    K = torch.empty((model.p, n), dtype=torch.float64, device=Fs.device)
+    dK = torch.empty((model.p, 9, n), dtype=torch.float64, device=Fs.device)
+    L.check(model.lib.pa_invariants(C.byref(model.desc), n, _p(Fs), _p(I_raw), _p(K), _p(dK), _stream()),
+            "pa_invariants")
+    return I_raw, K, dK
+
+
+def energy_stress_tangent(model: Model, F, prec="fp64", psi=True, P=True, A=True, soa=False,
+                          n_bad=None, workspace=None, out=None):
+    """Psi (n,), P (9, n), AA (81, n) in SoA layout (as returned by the
+    library).  ``F`` is (n, 3, 3) or, with soa=True, (9, n)."""
+    Fs = F if soa else _soa9(F)
+    n = Fs.shape[1]
+    dev = Fs.device
+    if out is None:
+        out = {}
+        if psi:
+            out["psi"] = torch.empty(n, dtype=torch.float64, device=dev)
+        if P:
+            out["P"] = torch.empty((9, n), dtype=torch.float64, device=dev)
+        if A:
+            out["A"] = torch.empty((81, n), dtype=torch.float64, device=dev)
+    ws_bytes = model.lib.pa_material_workspace_bytes(C.byref(model.desc), n)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    L.check(model.lib.pa_energy_stress_tangent(
+        C.byref(model.desc), _p(model.prepared), _prec(prec), n, _p(Fs), _p(out.get("psi")), _p(out.get("P")),
+        _p(out.get("A")), _p(n_bad), _p(workspace), workspace.numel(), _stream()), "pa_energy_stress_tangent")
+    return out
+
+
+class FEMesh:
+    """Device-resident mesh: geometry, CSR pattern, element->CSR map and a
+    colouring.  Elements are renumbered colour by colour (``perm[i]`` is the
+    original id of element i) so every colour is a contiguous range."""
+
+    def __init__(self, X, conn, colour=None, device="cuda"):
+        self.lib = lib = L.load()
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        n_el, nen = conn.shape
+        self.nen, self.n_el, self.n_nodes = nen, n_el, X.shape[0]
+        self.nq = 8 if nen == 8 else 4
+        self.nd = 3 * nen
+        if colour is None:
+            colour = np.empty(n_el, dtype=np.int32)
+            nc = C.c_int32()
+            L.check(lib.pa_colour_elements(nen, n_el, self.n_nodes, conn.ctypes.data_as(C.c_void_p),
+                                           colour.ctypes.data_as(C.c_void_p), C.byref(nc)), "pa_colour_elements")
+        colour = np.asarray(colour, dtype=np.int32)
+        self.perm = np.argsort(colour, kind="stable").astype(np.int64)
+        self.conn_host = np.ascontiguousarray(conn[self.perm])
+        counts = np.bincount(colour, minlength=int(colour.max()) + 1 if n_el else 0)
+        self.colour_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        self.n_colours = len(counts)
+        dev = torch.device(device)
+        self.device = dev
+        self.X = torch.tensor(X.T.copy(), device=dev)
+        self.conn = torch.tensor(self.conn_host.T.copy(), device=dev)
+        self.dNdX = torch.empty((self.nq, nen, 3, n_el), dtype=torch.float64, device=dev)
+        self.w = torch.empty((self.nq, n_el), dtype=torch.float64, device=dev)
+        self.n_bad = torch.zeros(1, dtype=torch.int32, device=dev)
+        L.check(lib.pa_mesh_geometry(nen, n_el, self.n_nodes, _p(self.X), _p(self.conn), _p(self.dNdX), _p(self.w),
+                                     _p(self.n_bad), _stream()), "pa_mesh_geometry")
+        nnz = C.c_int64()
+        cp = self.conn_host.ctypes.data_as(C.c_void_p)
+        L.check(lib.pa_csr_pattern(nen, n_el, self.n_nodes, cp, None, None, C.byref(nnz)), "pa_csr_pattern")
+        self.nnz = nnz.value
+        row_ptr = np.empty(3 * self.n_nodes + 1, dtype=np.int64)
+        col = np.empty(self.nnz, dtype=np.int32)
+        L.check(lib.pa_csr_pattern(nen, n_el, self.n_nodes, cp, row_ptr.ctypes.data_as(C.c_void_p),
+                                   col.ctypes.data_as(C.c_void_p), C.byref(nnz)), "pa_csr_pattern")
+        self.row_ptr_host, self.col_host = row_ptr, col
+        self.row_ptr = torch.tensor(row_ptr, device=dev)
+        self.col = torch.tensor(col, device=dev)
+        self.e2csr = torch.empty((n_el, nen, nen), dtype=torch.int32, device=dev)
+        self.c_mesh = L.Mesh(n_el, self.n_nodes, nen, self.nq, self.conn.data_ptr(), self.dNdX.data_ptr(),
+                             self.w.data_ptr())
+        self.c_csr = L.Csr(3 * self.n_nodes, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                           self.e2csr.data_ptr())
+        L.check(lib.pa_element_csr_map(C.byref(self.c_mesh), C.byref(self.c_csr), _p(self.e2csr), _stream()),
+                "pa_element_csr_map")
+        self.c_col = L.Colouring(self.n_colours, self.colour_ptr.ctypes.data_as(C.c_void_p).value, None)
+
+    def workspace_bytes(self, model: Model) -> int:
+        return self.lib.pa_element_workspace_bytes(C.byref(model.desc), C.byref(self.c_mesh))
+
+
+def element_residual_stiffness(model: Model, mesh: FEMesh, u, prec="fp64", stiffness=True, workspace=None,
+                               r_e=None, K_e=None, n_bad=None):
+    """r_e (n_el, nd) and K_e (n_el, nd, nd) for the mesh's (colour-ordered) elements.
+    u: (n_nodes, 3) or (3 n_nodes,) displacement, dof = 3*node + i."""
+    u = u.reshape(-1).contiguous()
+    dev = u.device
+    if r_e is None:
+        r_e = torch.empty((mesh.n_el, mesh.nd), dtype=torch.float64, device=dev)
+    if stiffness and K_e is None:
+        K_e = torch.empty((mesh.n_el, mesh.nd, mesh.nd), dtype=torch.float64, device=dev)
+    nb = mesh.workspace_bytes(model)
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+    L.check(model.lib.pa_element_residual_stiffness(
+        C.byref(model.desc), _p(model.prepared), _prec(prec), C.byref(mesh.c_mesh), _p(u), _p(r_e),
+        _p(K_e if stiffness else None), _p(n_bad), _p(workspace), workspace.numel(), _stream()),
+        "pa_element_residual_stiffness")
+    return r_e, K_e
+
+
+def assemble_csr(mesh: FEMesh, r_e, K_e, r=None, vals=None, zero_first=True):
+    """Coloured scatter-assembly into the global residual and CSR values."""
+    dev = mesh.device
+    if r is None and r_e is not None:
+        r = torch.empty(3 * mesh.n_nodes, dtype=torch.float64, device=dev)
+    if vals is None and K_e is not None:
+        vals = torch.empty(mesh.nnz, dtype=torch.float64, device=dev)
+    L.check(mesh.lib.pa_assemble_csr(C.byref(mesh.c_mesh), C.byref(mesh.c_col), C.byref(mesh.c_csr), _p(r_e),
+                                     _p(K_e), _p(r), _p(vals), int(bool(zero_first)), _stream()), "pa_assemble_csr")
+    return r, vals
+
+
+def tangent_build(model: Model, mesh: FEMesh, u, prec="fp64", workspace=None, bufs=None):
+    """One Newton tangent build: u -> (r, CSR values)."""
+    bufs = bufs if bufs is not None else {}
+    r_e, K_e = element_residual_stiffness(model, mesh, u, prec, workspace=workspace,
+                                          r_e=bufs.get("r_e"), K_e=bufs.get("K_e"))
+    r, vals = assemble_csr(mesh, r_e, K_e, r=bufs.get("r"), vals=bufs.get("vals"))
+    bufs.update(r_e=r_e, K_e=K_e, r=r, vals=vals)
+    return r, vals
+
+
+def param_backward(model: Model, F, P_bar, prec="fp32", soa=False, workspace=None):
+    """theta_bar = sum_q (dP_q/dtheta)^T P_bar_q (raw network)."""
+    Fs = F if soa else _soa9(F)
+    Pb = P_bar if soa else _soa9(P_bar)
+    n = Fs.shape[1]
+    out = torch.empty(model.n_params, dtype=torch.float64, device=Fs.device)
+    nb = model.lib.pa_param_backward_workspace(C.byref(model.desc), _prec(prec), n)
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=Fs.device)
+    L.check(model.lib.pa_param_backward(C.byref(model.desc), _p(model.prepared), _prec(prec), n, _p(Fs), _p(Pb),
+                                        _p(out), _p(workspace), workspace.numel(), _stream()), "pa_param_backward")
+    return out

@@ -1,0 +1,401 @@
+// C ABI of the library (include/pa.h): argument checks on the host, then
+// asynchronous kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pa.h"
+#include "pa_internal.h"
+
+namespace pa {
+int host_csr_pattern(int nen, int64_t n_el, int64_t n_nodes, const int32_t* conn, int64_t* row_ptr,
+                     int32_t* col, int64_t* nnz_out);
+int host_colour(int nen, int64_t n_el, int64_t n_nodes, const int32_t* conn, int32_t* colour,
+                int32_t* n_colours);
+}
+
+using namespace pa;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_check(const char* where) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(PA_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+  return PA_OK;
+}
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+// ---- optional per-kernel event timing
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+bool g_prof = false;
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+size_t g_pool_next = 0;
+
+hipEvent_t pool_event() {
+  if (g_pool_next == g_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_pool.push_back(e);
+  }
+  return g_pool[g_pool_next++];
+}
+
+struct Prof {
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Prof(const char* n, hipStream_t st) : name(n), s(st) {
+    if (g_prof && (a = pool_event())) (void)hipEventRecord(a, s);
+  }
+  ~Prof() {
+    if (!a) return;
+    hipEvent_t b = pool_event();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    g_recs.push_back({name, a, b});
+  }
+};
+
+inline int npair_of(int n_sv) { return n_sv * (n_sv + 1) / 2; }
+
+int check_desc(const pa_model_desc* d) {
+  if (!d) return fail(PA_ERR_ARG, "desc is NULL");
+  if (d->n_sv < 0 || d->n_sv > 2) return fail(PA_ERR_ARG, "n_sv must be 0, 1 or 2 (got %d)", d->n_sv);
+  if (d->n_hidden < 2) return fail(PA_ERR_ARG, "n_hidden must be >= 2 (got %d)", d->n_hidden);
+  if (d->width <= 0 || d->width % 16) return fail(PA_ERR_ARG, "width must be a positive multiple of 16 (got %d)", d->width);
+  if (d->activation != PA_ACT_SOFTPLUS) return fail(PA_ERR_ARG, "unknown activation %d", d->activation);
+  if (d->algorithm != PA_ALGO_FORWARD && d->algorithm != PA_ALGO_ADJOINT)
+    return fail(PA_ERR_ARG, "unknown algorithm %d", d->algorithm);
+  for (int i = 0; i < d->n_sv; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (!std::isfinite(d->A[i][j])) return fail(PA_ERR_ARG, "structural vector %d is not finite", i);
+  const int p = 3 + 2 * npair_of(d->n_sv);
+  if (!mlp_supported(d->width, d->n_hidden, p))
+    return fail(PA_ERR_UNSUPPORTED, "no kernel for width %d, %d hidden layers, %d inputs", d->width, d->n_hidden, p);
+  return PA_OK;
+}
+
+ModelConst model_const(const pa_model_desc* d) {
+  ModelConst mc{};
+  for (int i = 0; i < d->n_sv; ++i)
+    for (int j = 0; j < 3; ++j) mc.A[i][j] = d->A[i][j];
+  int q = 0;
+  for (int i = 0; i < d->n_sv; ++i)
+    for (int j = i; j < d->n_sv; ++j, ++q)
+      mc.AdotA[q] = d->A[i][0] * d->A[j][0] + d->A[i][1] * d->A[j][1] + d->A[i][2] * d->A[j][2];
+  return mc;
+}
+
+inline int p_of(const pa_model_desc* d) { return 3 + 2 * npair_of(d->n_sv); }
+
+inline PrepLayout layout_of(const pa_model_desc* d) { return prep_layout(d->width, d->n_hidden, p_of(d)); }
+
+inline int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+// workspace of the material pipeline: K [p][n], N-derivatives [NOUT][n]
+int64_t material_ws(const pa_model_desc* d, int64_t n) {
+  const int p = p_of(d);
+  const int nout = 1 + p + p * (p + 1) / 2;
+  return al(8 * (int64_t)p * n) + al(8 * (int64_t)nout * n);
+}
+
+int check_prec(int prec) {
+  if (prec < PA_FP64 || prec > PA_BF16_CORR) return fail(PA_ERR_ARG, "unknown precision %d", prec);
+  return PA_OK;
+}
+
+// F -> (psi, P, AA) through features, network and chain rule.
+int run_material(const pa_model_desc* d, const void* prepared, int prec, int64_t n, const double* F,
+                 double* psi, double* P, double* A, int32_t* n_bad, unsigned char* ws, hipStream_t s) {
+  const int p = p_of(d);
+  const PrepLayout lay = layout_of(d);
+  const ModelConst mc = model_const(d);
+  double* K = (double*)ws;
+  double* Nout = (double*)(ws + al(8 * (int64_t)p * n));
+  const unsigned char* prep = (const unsigned char*)prepared;
+  {
+    Prof pr("features", s);
+    if (launch_features(d->n_sv, n, F, mc, K, n_bad, s)) return fail(PA_ERR_ARG, "bad n_sv");
+  }
+  int rc;
+  {
+    Prof pr(d->algorithm == PA_ALGO_ADJOINT ? "mlp_adjoint" : "mlp_forward", s);
+    rc = launch_mlp(lay, prec, d->algorithm, prep, n, K, Nout, s);
+  }
+  if (rc == -2) return fail(PA_ERR_UNSUPPORTED, "network algorithm %d not available", d->algorithm);
+  if (rc) return fail(PA_ERR_ARG, "bad network configuration");
+  {
+    Prof pr("chain", s);
+    if (launch_chain(d->n_sv, n, F, Nout, (const double*)(prep + lay.hdr), mc, psi, P, A, n_bad, s))
+      return fail(PA_ERR_ARG, "bad n_sv");
+  }
+  return hip_check("material kernels");
+}
+
+int check_mesh(const pa_mesh* m) {
+  if (!m) return fail(PA_ERR_ARG, "mesh is NULL");
+  if (!((m->nen == 8 && m->nq == 8) || (m->nen == 10 && m->nq == 4)))
+    return fail(PA_ERR_ARG, "unsupported element: nen=%d nq=%d (hex8: 8/8, tet10: 10/4)", m->nen, m->nq);
+  if (m->n_el < 0 || m->n_nodes < 0) return fail(PA_ERR_ARG, "negative mesh size");
+  if (m->n_el > 0 && (!m->conn || !m->dNdX || !m->w)) return fail(PA_ERR_ARG, "mesh arrays missing");
+  if ((int64_t)m->n_el * m->nq > ((int64_t)1 << 40)) return fail(PA_ERR_ARG, "mesh too large");
+  return PA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pa_version(void) { return "pa 0.1 (gfx950)"; }
+
+const char* pa_last_error(void) { return g_err.c_str(); }
+
+const char* pa_status_string(int s) {
+  switch (s) {
+    case PA_OK: return "ok";
+    case PA_ERR_ARG: return "invalid argument";
+    case PA_ERR_UNSUPPORTED: return "unsupported configuration";
+    case PA_ERR_HIP: return "HIP runtime error";
+    case PA_ERR_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+int32_t pa_num_inputs(const pa_model_desc* d) {
+  if (!d || d->n_sv < 0 || d->n_sv > 2) return -1;
+  return p_of(d);
+}
+
+int64_t pa_num_params(const pa_model_desc* d) {
+  if (!d || d->n_sv < 0 || d->n_sv > 2 || d->width <= 0 || d->n_hidden < 1) return -1;
+  return theta_layout(d->width, d->n_hidden, p_of(d), d->has_bias ? 1 : 0).total;
+}
+
+int32_t pa_supported(const pa_model_desc* d) { return check_desc(d) == PA_OK ? 1 : 0; }
+
+size_t pa_prepared_bytes(const pa_model_desc* d) {
+  if (check_desc(d) != PA_OK) return 0;
+  return (size_t)layout_of(d).total;
+}
+
+int pa_prepare_params(const pa_model_desc* d, const double* theta, void* prepared, void* stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (!theta || !prepared) return fail(PA_ERR_ARG, "theta and prepared must be non-NULL");
+  const PrepLayout lay = layout_of(d);
+  const ThetaLayout tl = theta_layout(d->width, d->n_hidden, p_of(d), d->has_bias ? 1 : 0);
+  rc = launch_prepare(lay, tl, theta, (unsigned char*)prepared, d->normalize ? 1 : 0, npair_of(d->n_sv), S(stream));
+  if (rc) return fail(PA_ERR_UNSUPPORTED, "prepare failed (%d)", rc);
+  return hip_check("pa_prepare_params");
+}
+
+int pa_invariants(const pa_model_desc* d, int64_t n, const double* F, double* I_raw, double* K,
+                  double* dKdF, void* stream) {
+  if (!d || d->n_sv < 0 || d->n_sv > 2) return fail(PA_ERR_ARG, "bad desc / n_sv");
+  if (n < 0) return fail(PA_ERR_ARG, "n_qp < 0");
+  if (n > 0 && !F) return fail(PA_ERR_ARG, "F is NULL");
+  if (n == 0) return PA_OK;
+  launch_invariants(d->n_sv, n, F, model_const(d), I_raw, K, dKdF, nullptr, S(stream));
+  return hip_check("pa_invariants");
+}
+
+size_t pa_material_workspace_bytes(const pa_model_desc* d, int64_t n) {
+  if (!d || d->n_sv < 0 || d->n_sv > 2 || n < 0) return 0;
+  return (size_t)material_ws(d, n);
+}
+
+int pa_energy_stress_tangent(const pa_model_desc* d, const void* prepared, int prec, int64_t n,
+                             const double* F, double* psi, double* P, double* A, int32_t* n_bad,
+                             void* workspace, size_t ws_bytes, void* stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if ((rc = check_prec(prec))) return rc;
+  if (n < 0) return fail(PA_ERR_ARG, "n_qp < 0");
+  if (n == 0) return PA_OK;
+  if (!prepared || !F) return fail(PA_ERR_ARG, "prepared and F must be non-NULL");
+  if (!workspace || (int64_t)ws_bytes < material_ws(d, n))
+    return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)material_ws(d, n));
+  return run_material(d, prepared, prec, n, F, psi, P, A, n_bad, (unsigned char*)workspace, S(stream));
+}
+
+int pa_mesh_geometry(int32_t nen, int64_t n_el, int64_t n_nodes, const double* X, const int32_t* conn,
+                     double* dNdX, double* w, int32_t* n_bad, void* stream) {
+  if (nen != 8 && nen != 10) return fail(PA_ERR_ARG, "nen must be 8 or 10");
+  if (n_el < 0 || n_nodes < 0) return fail(PA_ERR_ARG, "negative size");
+  if (n_el == 0) return PA_OK;
+  if (!X || !conn || !dNdX || !w) return fail(PA_ERR_ARG, "NULL array");
+  launch_geometry(nen, n_el, n_nodes, X, conn, dNdX, w, n_bad, S(stream));
+  return hip_check("pa_mesh_geometry");
+}
+
+size_t pa_element_workspace_bytes(const pa_model_desc* d, const pa_mesh* m) {
+  if (!d || !m || d->n_sv < 0 || d->n_sv > 2) return 0;
+  const int64_t n = m->n_el * m->nq;
+  // F [9][n], P [9][n], AA [81][n], then the material workspace
+  return (size_t)(al(8 * 9 * n) * 2 + al(8 * 81 * n) + material_ws(d, n));
+}
+
+int pa_element_residual_stiffness(const pa_model_desc* d, const void* prepared, int prec, const pa_mesh* m,
+                                  const double* u, double* r_e, double* K_e, int32_t* n_bad,
+                                  void* workspace, size_t ws_bytes, void* stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_mesh(m))) return rc;
+  if (m->n_el == 0) return PA_OK;
+  if (!prepared || !u || !r_e) return fail(PA_ERR_ARG, "prepared, u and r_e must be non-NULL");
+  const int64_t need = (int64_t)pa_element_workspace_bytes(d, m);
+  if (!workspace || (int64_t)ws_bytes < need) return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
+  const int64_t n = m->n_el * m->nq;
+  unsigned char* ws = (unsigned char*)workspace;
+  double* F = (double*)ws;
+  double* P = (double*)(ws + al(8 * 9 * n));
+  double* A = (double*)(ws + 2 * al(8 * 9 * n));
+  unsigned char* mws = ws + 2 * al(8 * 9 * n) + al(8 * 81 * n);
+  hipStream_t s = S(stream);
+  {
+    Prof pr("gather_F", s);
+    launch_gather_F(m->nen, m->nq, m->n_el, m->conn, m->dNdX, u, F, s);
+  }
+  if ((rc = run_material(d, prepared, prec, n, F, nullptr, P, K_e ? A : nullptr, n_bad, mws, s))) return rc;
+  {
+    Prof pr("integrate", s);
+    launch_integrate(m->nen, m->nq, m->n_el, m->dNdX, m->w, P, A, r_e, K_e, s);
+  }
+  return hip_check("pa_element_residual_stiffness");
+}
+
+int pa_csr_pattern(int32_t nen, int64_t n_el, int64_t n_nodes, const int32_t* conn_host, int64_t* row_ptr,
+                   int32_t* col, int64_t* nnz) {
+  if (nen != 8 && nen != 10) return fail(PA_ERR_ARG, "nen must be 8 or 10");
+  if (!conn_host || !nnz || n_el < 0 || n_nodes < 0) return fail(PA_ERR_ARG, "bad arguments");
+  if (3 * n_nodes >= ((int64_t)1 << 31)) return fail(PA_ERR_ARG, "too many dofs for 32-bit column indices");
+  if (col && !row_ptr) return fail(PA_ERR_ARG, "col requires row_ptr");
+  if (host_csr_pattern(nen, n_el, n_nodes, conn_host, row_ptr, col, nnz))
+    return fail(PA_ERR_ARG, "connectivity refers to a node outside [0, n_nodes)");
+  return PA_OK;
+}
+
+int pa_colour_elements(int32_t nen, int64_t n_el, int64_t n_nodes, const int32_t* conn_host, int32_t* colour,
+                       int32_t* n_colours) {
+  if (nen != 8 && nen != 10) return fail(PA_ERR_ARG, "nen must be 8 or 10");
+  if (!conn_host || !colour || !n_colours || n_el < 0) return fail(PA_ERR_ARG, "bad arguments");
+  if (host_colour(nen, n_el, n_nodes, conn_host, colour, n_colours))
+    return fail(PA_ERR_ARG, "connectivity refers to a node outside [0, n_nodes)");
+  return PA_OK;
+}
+
+int pa_element_csr_map(const pa_mesh* m, const pa_csr* c, int32_t* e2csr, void* stream) {
+  if (!m || !c || !e2csr) return fail(PA_ERR_ARG, "NULL argument");
+  if (m->nen != 8 && m->nen != 10) return fail(PA_ERR_ARG, "nen must be 8 or 10");
+  if (!c->row_ptr || !c->col || !m->conn) return fail(PA_ERR_ARG, "csr/conn arrays missing");
+  launch_csr_map(m->nen, m->n_el, m->conn, c->row_ptr, c->col, e2csr, S(stream));
+  return hip_check("pa_element_csr_map");
+}
+
+int pa_assemble_csr(const pa_mesh* m, const pa_colouring* col, const pa_csr* c, const double* r_e,
+                    const double* K_e, double* r, double* vals, int32_t zero_first, void* stream) {
+  if (!m || !col || !c) return fail(PA_ERR_ARG, "NULL argument");
+  if (m->nen != 8 && m->nen != 10) return fail(PA_ERR_ARG, "nen must be 8 or 10");
+  if (c->n_rows != 3 * m->n_nodes) return fail(PA_ERR_ARG, "csr has %lld rows, mesh needs %lld", (long long)c->n_rows, (long long)(3 * m->n_nodes));
+  if (col->n_colours < 0 || (col->n_colours > 0 && !col->colour_ptr)) return fail(PA_ERR_ARG, "bad colouring");
+  if (col->n_colours > 0 && (col->colour_ptr[0] != 0 || col->colour_ptr[col->n_colours] != m->n_el))
+    return fail(PA_ERR_ARG, "colour_ptr must start at 0 and end at n_el");
+  for (int i = 0; i < col->n_colours; ++i)
+    if (col->colour_ptr[i + 1] < col->colour_ptr[i]) return fail(PA_ERR_ARG, "colour_ptr not monotone");
+  const bool doK = K_e && vals;
+  const bool doR = r_e && r;
+  if (doK && (!c->row_ptr || !c->e2csr)) return fail(PA_ERR_ARG, "csr row_ptr and e2csr needed for K");
+  hipStream_t s = S(stream);
+  if (zero_first) {
+    Prof pr("fill", s);
+    if (r) launch_fill(r, c->n_rows, 0.0, s);
+    if (vals) launch_fill(vals, c->nnz, 0.0, s);
+  }
+  for (int k = 0; k < col->n_colours; ++k) {
+    Prof pr("assemble", s);
+    const int64_t b = col->colour_ptr[k], cnt = col->colour_ptr[k + 1] - b;
+    launch_assemble(m->nen, b, cnt, col->elem_perm, m->n_el, m->conn, c->row_ptr, c->e2csr,
+                    doR ? r_e : nullptr, doK ? K_e : nullptr, doR ? r : nullptr, doK ? vals : nullptr, s);
+  }
+  return hip_check("pa_assemble_csr");
+}
+
+size_t pa_param_backward_workspace(const pa_model_desc* d, int prec, int64_t n) {
+  (void)d; (void)prec; (void)n;
+  return 0;
+}
+
+int pa_param_backward(const pa_model_desc* d, const void* prepared, int prec, int64_t n, const double* F,
+                      const double* P_bar, double* theta_bar, void* workspace, size_t ws_bytes, void* stream) {
+  (void)d; (void)prepared; (void)prec; (void)n; (void)F; (void)P_bar; (void)theta_bar; (void)workspace;
+  (void)ws_bytes; (void)stream;
+  return fail(PA_ERR_UNSUPPORTED, "pa_param_backward not available yet");
+}
+
+int pa_profile_enable(int32_t on) {
+  g_prof = on != 0;
+  if (g_prof) {
+    g_recs.clear();
+    g_pool_next = 0;
+  }
+  return PA_OK;
+}
+
+namespace {
+struct Agg {
+  double ms = 0.0;
+  int64_t n = 0;
+};
+std::vector<std::pair<std::string, Agg>> g_agg;
+}  // namespace
+
+int32_t pa_profile_count(void) {
+  std::map<std::string, Agg> m;
+  for (auto& r : g_recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return fail(PA_ERR_HIP, "event synchronise failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(PA_ERR_HIP, "event timing failed");
+    Agg& a = m[r.name];
+    a.ms += ms;
+    a.n += 1;
+  }
+  g_agg.assign(m.begin(), m.end());
+  return (int32_t)g_agg.size();
+}
+
+int pa_profile_get(int32_t i, const char** name, double* total_ms, int64_t* launches) {
+  if (i < 0 || i >= (int32_t)g_agg.size()) return fail(PA_ERR_ARG, "profile index out of range");
+  static thread_local std::string nm;
+  nm = g_agg[i].first;
+  if (name) *name = nm.c_str();
+  if (total_ms) *total_ms = g_agg[i].second.ms;
+  if (launches) *launches = g_agg[i].second.n;
+  return PA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+// Kernels for the FP64 kinematic layer (features, invariants) and the chain
+// rule that turns network derivatives into P and dP/dF.  One quadrature
+// point per lane; all per-point arrays are SoA ([component][n]) so every
+// load and store is coalesced.
+#include "kinematics.h"
+#include "pa_internal.h"
+
+namespace pa {
+
+// Wave-aggregated increment of an optional device counter.
+__device__ inline void count_bad(int32_t* n_bad, bool bad) {
+  if (!n_bad) return;
+  const unsigned long long m = __ballot(bad);
+  if (m && (threadIdx.x & 63) == (__ffsll((long long)m) - 1)) atomicAdd(n_bad, (int32_t)__popcll(m));
+}
+
+__device__ inline bool finite9(const double* F) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) ok = ok && isfinite(F[i]);
+  return ok;
+}
+
+template <int NSV>
+__global__ void __launch_bounds__(256) k_invariants(int64_t n, const double* __restrict__ F,
+                                                    ModelConst mc, double* __restrict__ I_raw,
+                                                    double* __restrict__ K, double* __restrict__ dKdF,
+                                                    int32_t* n_bad) {
+  constexpr int NP = Feat<NSV>::NP;
+  constexpr int P = Feat<NSV>::P;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = t < n;
+  double f[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = in ? F[i * n + t] : (i % 4 == 0 ? 1.0 : 0.0);
+  Kin k;
+  kin_compute<NSV>(f, mc, k);
+  count_bad(n_bad, in && !(k.J > 0.0 && finite9(f)));
+  if (!in) return;
+  if (I_raw) {
+    I_raw[0 * n + t] = k.I1;
+    I_raw[1 * n + t] = k.I2;
+    I_raw[2 * n + t] = k.I3;
+    I_raw[3 * n + t] = k.J;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      I_raw[(4 + q) * n + t] = k.I4[q];
+      I_raw[(4 + NP + q) * n + t] = k.I5[q];
+    }
+  }
+  if (K) {
+    double kf[P];
+    kin_features<NSV>(k, mc, kf);
+#pragma unroll
+    for (int m = 0; m < P; ++m) K[m * n + t] = kf[m];
+  }
+  if (dKdF) {
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      double d[6];
+      kin_dfeature<NSV>(k, mc, m, d);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+          const double v = 2.0 * (k.F[3 * i] * d[VI(0, J)] + k.F[3 * i + 1] * d[VI(1, J)] + k.F[3 * i + 2] * d[VI(2, J)]);
+          dKdF[((int64_t)m * 9 + 3 * i + J) * n + t] = v;
+        }
+    }
+  }
+}
+
+// Network outputs in SoA: row 0 = N, rows 1..P = dN/dK_m, then the packed
+// upper triangle of d2N/dK_m dK_n (row-major, m <= n).
+template <int NSV>
+__global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restrict__ F,
+                                               const double* __restrict__ Nout, const double* __restrict__ N0,
+                                               ModelConst mc, double* __restrict__ psi,
+                                               double* __restrict__ Pout, double* __restrict__ Aout,
+                                               int32_t* n_bad) {
+  constexpr int P = Feat<NSV>::P;
+  constexpr int P2 = P * (P + 1) / 2;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double f[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = F[i * n + t];
+  Kin k;
+  kin_compute<NSV>(f, mc, k);
+  if (psi) psi[t] = Nout[t] - N0[0];
+  if (!Pout && !Aout) return;
+  double dN[P], d2N[P2];
+#pragma unroll
+  for (int m = 0; m < P; ++m) dN[m] = Nout[(1 + m) * n + t];
+  if (Aout) {
+#pragma unroll
+    for (int m = 0; m < P2; ++m) d2N[m] = Nout[(1 + P + m) * n + t];
+  } else {
+#pragma unroll
+    for (int m = 0; m < P2; ++m) d2N[m] = 0.0;
+  }
+  double S[6], CCt[21];
+  chain_material<NSV>(k, mc, dN, d2N, S, CCt);
+  push_material(
+      k, S, CCt,
+      [&](int c, double v) { if (Pout) Pout[(int64_t)c * n + t] = v; },
+      [&](int c, double v) { if (Aout) Aout[(int64_t)c * n + t] = v; });
+  (void)n_bad;
+}
+
+// Features only (input to the network kernels).
+template <int NSV>
+__global__ void __launch_bounds__(256) k_features(int64_t n, const double* __restrict__ F, ModelConst mc,
+                                                  double* __restrict__ K, int32_t* n_bad) {
+  constexpr int P = Feat<NSV>::P;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = t < n;
+  double f[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = in ? F[i * n + t] : (i % 4 == 0 ? 1.0 : 0.0);
+  Kin k;
+  kin_compute<NSV>(f, mc, k);
+  count_bad(n_bad, in && !(k.J > 0.0 && finite9(f)));
+  if (!in) return;
+  double kf[P];
+  kin_features<NSV>(k, mc, kf);
+#pragma unroll
+  for (int m = 0; m < P; ++m) K[m * n + t] = kf[m];
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+int launch_invariants(int nsv, int64_t n, const double* F, const ModelConst& mc, double* I_raw,
+                      double* K, double* dKdF, int32_t* n_bad, hipStream_t s) {
+  if (n == 0) return 0;
+  switch (nsv) {
+    case 0: k_invariants<0><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, I_raw, K, dKdF, n_bad); break;
+    case 1: k_invariants<1><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, I_raw, K, dKdF, n_bad); break;
+    case 2: k_invariants<2><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, I_raw, K, dKdF, n_bad); break;
+    default: return -1;
+  }
+  return 0;
+}
+
+int launch_features(int nsv, int64_t n, const double* F, const ModelConst& mc, double* K,
+                    int32_t* n_bad, hipStream_t s) {
+  if (n == 0) return 0;
+  switch (nsv) {
+    case 0: k_features<0><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, K, n_bad); break;
+    case 1: k_features<1><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, K, n_bad); break;
+    case 2: k_features<2><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, K, n_bad); break;
+    default: return -1;
+  }
+  return 0;
+}
+
+int launch_chain(int nsv, int64_t n, const double* F, const double* Nout, const double* N0,
+                 const ModelConst& mc, double* psi, double* P, double* A, int32_t* n_bad, hipStream_t s) {
+  if (n == 0) return 0;
+  switch (nsv) {
+    case 0: k_chain<0><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, P, A, n_bad); break;
+    case 1: k_chain<1><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, P, A, n_bad); break;
+    case 2: k_chain<2><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, P, A, n_bad); break;
+    default: return -1;
+  }
+  return 0;
+}
+
+}  // namespace pa

@@ -1,0 +1,687 @@
+// Inner network (MICNN, eq. icnn of App. B.2) with its input gradient and
+// Hessian, evaluated by the one-pass forward mode of Alg. 4 on the matrix
+// cores of gfx950.
+//
+// Data layout.  A workgroup owns a tile of 16 quadrature points, which form
+// the N dimension (16 columns) of every matrix-core instruction.  The h
+// neurons of each hidden layer are split into h/16 blocks of 16 rows; wave w
+// computes rows 16w..16w+15 of layers 2..L.  Layer 1 (h x p, cheap) is
+// evaluated by every wave for all rows so that its outputs are already in the
+// register positions the next instruction reads: the result of one
+// instruction (column = point, rows per lane) is fed back as the B operand of
+// the next with the K index permuted to match, so activations never leave
+// registers between layer 1 and layer 2.  Between layers k >= 2 the activated
+// rows are exchanged through LDS.
+//
+// Columns.  Alg. 4 carries, for every point, the value column z, the p
+// gradient columns dz/dK_m and the p(p+1)/2 Hessian columns d2z/dK_m dK_n.
+// They are streamed through the layers in that order: the value column
+// leaves sigma(y_k) and F''(y_k) in registers, the gradient columns leave
+// dy_k/dK_m, and each Hessian column then needs only
+//   d2z_k = F'(y_k) (A_k d2z_{k-1}) + F''(y_k) dy_k/dK_m dy_k/dK_n.
+// The output layer N = a.z_L + b.K is applied to every column as it leaves
+// layer L (cross-lane and cross-wave sums in a fixed order).
+#include <type_traits>
+#include <utility>
+
+#include "pa_internal.h"
+
+namespace pa {
+
+// ---------------------------------------------------------------- layouts
+static inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+PrepLayout prep_layout(int H, int L, int P) {
+  PrepLayout l{};
+  l.H = H; l.L = L; l.P = P;
+  l.MB = H / 16;
+  l.S1 = (P + 3) / 4;
+  l.SH = H / 4;
+  l.SHB = (H + 31) / 32;
+  l.NOUT = 1 + P + P * (P + 1) / 2;
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) { int64_t r = o; o = align256(o + bytes); return r; };
+  l.hdr = take(8 * 8);
+  l.d_a = take(8 * H);
+  l.d_b = take(8 * P);
+  l.d_c = take(8 * (int64_t)L * H);
+  l.d_W1t = take(8 * (int64_t)P * H);
+  l.d_Bt = take(8 * (int64_t)L * P * H);
+  l.f_a = take(4 * H);
+  l.f_c = take(4 * (int64_t)L * H);
+  l.f_W1t = take(4 * (int64_t)P * H);
+  l.f_Bt = take(4 * (int64_t)L * P * H);
+  l.x_W1 = take(8 * (int64_t)l.MB * l.S1 * 64);
+  l.x_A = take(8 * (int64_t)L * l.MB * l.SH * 64);
+  l.x_B = take(8 * (int64_t)L * l.MB * l.S1 * 64);
+  l.y_W1 = take(4 * (int64_t)l.MB * l.S1 * 64);
+  l.y_A = take(4 * (int64_t)L * l.MB * l.SH * 64);
+  l.y_B = take(4 * (int64_t)L * l.MB * l.S1 * 64);
+  l.z_W1 = take(16 * (int64_t)l.MB * 64);
+  l.z_A = take(16 * (int64_t)L * l.MB * l.SHB * 64);
+  l.z_B = take(16 * (int64_t)L * l.MB * 64);
+  l.k0 = take(8 * (int64_t)P * 16);
+  l.nout = take(8 * (int64_t)l.NOUT * 16);
+  l.total = o;
+  return l;
+}
+
+ThetaLayout theta_layout(int H, int L, int P, int has_bias) {
+  ThetaLayout t{};
+  t.H = H; t.L = L; t.P = P; t.has_bias = has_bias;
+  int64_t o = 0;
+  t.W1 = o; o += (int64_t)H * P;
+  t.c1 = has_bias ? o : -1; o += has_bias ? H : 0;
+  for (int k = 2; k <= L; ++k) {
+    t.A[k] = o; o += (int64_t)H * H;
+    t.B[k] = o; o += (int64_t)H * P;
+    t.c[k] = has_bias ? o : -1; o += has_bias ? H : 0;
+  }
+  t.a = o; o += H;
+  t.b = o; o += P;
+  t.total = o;
+  return t;
+}
+
+// ---------------------------------------------------------------- prepare
+__device__ inline double th_w(const double* th, const ThetaLayout& t, int k, int row, int col) {
+  return (k == 1) ? th[t.W1 + (int64_t)row * t.P + col] : th[t.A[k] + (int64_t)row * t.H + col];
+}
+__device__ inline double th_skip(const double* th, const ThetaLayout& t, int k, int row, int m) {
+  return th[t.B[k] + (int64_t)row * t.P + m];
+}
+__device__ inline double th_c(const double* th, const ThetaLayout& t, int k, int row) {
+  const int64_t o = (k == 1) ? t.c1 : t.c[k];
+  return o < 0 ? 0.0 : th[o + row];
+}
+
+__global__ void k_prep_tables(const double* __restrict__ th, ThetaLayout t, PrepLayout l,
+                              unsigned char* __restrict__ prep) {
+  const int H = l.H, P = l.P, L = l.L;
+  double* d_a = (double*)(prep + l.d_a);
+  double* d_b = (double*)(prep + l.d_b);
+  double* d_c = (double*)(prep + l.d_c);
+  double* d_W1t = (double*)(prep + l.d_W1t);
+  double* d_Bt = (double*)(prep + l.d_Bt);
+  float* f_a = (float*)(prep + l.f_a);
+  float* f_c = (float*)(prep + l.f_c);
+  float* f_W1t = (float*)(prep + l.f_W1t);
+  float* f_Bt = (float*)(prep + l.f_Bt);
+  const int64_t total = H + P + (int64_t)L * H + (int64_t)P * H + (int64_t)L * P * H + 8 + (int64_t)P * 16;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j = i;
+    if (j < H) { double v = th[t.a + j]; d_a[j] = v; f_a[j] = (float)v; continue; }
+    j -= H;
+    if (j < P) { d_b[j] = th[t.b + j]; continue; }
+    j -= P;
+    if (j < (int64_t)L * H) {
+      const int k = (int)(j / H) + 1, row = (int)(j % H);
+      const double v = th_c(th, t, k, row); d_c[j] = v; f_c[j] = (float)v; continue;
+    }
+    j -= (int64_t)L * H;
+    if (j < (int64_t)P * H) {
+      const int m = (int)(j / H), row = (int)(j % H);
+      const double v = th_w(th, t, 1, row, m); d_W1t[j] = v; f_W1t[j] = (float)v; continue;
+    }
+    j -= (int64_t)P * H;
+    if (j < (int64_t)L * P * H) {
+      const int k = (int)(j / ((int64_t)P * H)) + 1;
+      const int m = (int)((j / H) % P), row = (int)(j % H);
+      const double v = (k >= 2) ? th_skip(th, t, k, row, m) : 0.0;
+      d_Bt[j] = v; f_Bt[j] = (float)v; continue;
+    }
+    j -= (int64_t)L * P * H;
+    if (j < 8) { ((double*)(prep + l.hdr))[j] = 0.0; continue; }
+    j -= 8;
+    ((double*)(prep + l.k0))[j] = 0.0;
+  }
+}
+
+// Row of the 16x16 result held by lane group g in register v.
+__device__ inline int row64(int g, int v) { return g + 4 * v; }
+__device__ inline int row32(int g, int v) { return 4 * g + v; }
+
+__global__ void k_prep_frags(const double* __restrict__ th, ThetaLayout t, PrepLayout l,
+                             unsigned char* __restrict__ prep) {
+  const int H = l.H, P = l.P, L = l.L, MB = l.MB, S1 = l.S1, SH = l.SH, SHB = l.SHB;
+  double* xW1 = (double*)(prep + l.x_W1);
+  double* xA = (double*)(prep + l.x_A);
+  double* xB = (double*)(prep + l.x_B);
+  float* yW1 = (float*)(prep + l.y_W1);
+  float* yA = (float*)(prep + l.y_A);
+  float* yB = (float*)(prep + l.y_B);
+  __bf16* zW1 = (__bf16*)(prep + l.z_W1);
+  __bf16* zA = (__bf16*)(prep + l.z_A);
+  __bf16* zB = (__bf16*)(prep + l.z_B);
+  const int64_t nW1 = (int64_t)MB * S1 * 64;
+  const int64_t nA = (int64_t)L * MB * SH * 64;
+  const int64_t nB = (int64_t)L * MB * S1 * 64;
+  const int64_t nzW1 = (int64_t)MB * 64 * 8;
+  const int64_t nzA = (int64_t)L * MB * SHB * 64 * 8;
+  const int64_t nzB = (int64_t)L * MB * 64 * 8;
+  const int64_t total = nW1 + nA + nB + nzW1 + nzA + nzB;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j = idx;
+    if (j < nW1) {  // [mb][s][lane]: W1[16mb + i][4s + g]
+      const int lane = (int)(j % 64), s = (int)((j / 64) % S1), mb = (int)(j / (64 * S1));
+      const int i = lane & 15, g = lane >> 4, col = 4 * s + g;
+      const double v = col < P ? th_w(th, t, 1, 16 * mb + i, col) : 0.0;
+      xW1[j] = v; yW1[j] = (float)v; continue;
+    }
+    j -= nW1;
+    if (j < nA) {  // [k-1][w][s][lane]: A_k[16w + i][16mb + row(g, v)], s = 4mb + v
+      const int lane = (int)(j % 64), s = (int)((j / 64) % SH);
+      const int w = (int)((j / (64 * SH)) % MB), k = (int)(j / (64 * SH * MB)) + 1;
+      const int i = lane & 15, g = lane >> 4, mb = s / 4, v = s % 4;
+      double v64 = 0.0, v32 = 0.0;
+      if (k >= 2) {
+        v64 = th_w(th, t, k, 16 * w + i, 16 * mb + row64(g, v));
+        v32 = th_w(th, t, k, 16 * w + i, 16 * mb + row32(g, v));
+      }
+      xA[j] = v64; yA[j] = (float)v32; continue;
+    }
+    j -= nA;
+    if (j < nB) {  // [k-1][w][s][lane]: B_k[16w + i][4s + g]
+      const int lane = (int)(j % 64), s = (int)((j / 64) % S1);
+      const int w = (int)((j / (64 * S1)) % MB), k = (int)(j / (64 * S1 * MB)) + 1;
+      const int i = lane & 15, g = lane >> 4, col = 4 * s + g;
+      const double v = (k >= 2 && col < P) ? th_skip(th, t, k, 16 * w + i, col) : 0.0;
+      xB[j] = v; yB[j] = (float)v; continue;
+    }
+    j -= nB;
+    if (j < nzW1) {  // [mb][lane][e]: W1[16mb + i][8g + e]
+      const int e = (int)(j % 8), lane = (int)((j / 8) % 64), mb = (int)(j / 512);
+      const int i = lane & 15, g = lane >> 4, col = 8 * g + e;
+      zW1[j] = (__bf16)(float)(col < P ? th_w(th, t, 1, 16 * mb + i, col) : 0.0);
+      continue;
+    }
+    j -= nzW1;
+    if (j < nzA) {  // [k-1][w][s][lane][e]; source row 32s + 4g + e (e<4), 32s + 16 + 4g + e-4
+      const int e = (int)(j % 8), lane = (int)((j / 8) % 64), s = (int)((j / 512) % SHB);
+      const int w = (int)((j / (512 * SHB)) % MB), k = (int)(j / (512 * SHB * MB)) + 1;
+      const int i = lane & 15, g = lane >> 4;
+      const int r = (e < 4) ? 32 * s + 4 * g + e : 32 * s + 16 + 4 * g + (e - 4);
+      zA[j] = (__bf16)(float)((k >= 2 && r < H) ? th_w(th, t, k, 16 * w + i, r) : 0.0);
+      continue;
+    }
+    j -= nzA;
+    {  // [k-1][w][lane][e]: B_k[16w + i][8g + e]
+      const int e = (int)(j % 8), lane = (int)((j / 8) % 64);
+      const int w = (int)((j / 512) % MB), k = (int)(j / (512 * MB)) + 1;
+      const int i = lane & 15, g = lane >> 4, col = 8 * g + e;
+      zB[j] = (__bf16)(float)((k >= 2 && col < P) ? th_skip(th, t, k, 16 * w + i, col) : 0.0);
+    }
+  }
+}
+
+// Normalisation: N0 = N(0), kappa_q = dN/dK_{4,q}(0) + 2 dN/dK_{5,q}(0);
+// b_{4,q} -= kappa_q so that P(I) = 0; Psi = N - N0.
+__global__ void k_prep_fold(PrepLayout l, unsigned char* __restrict__ prep, int normalize, int npair) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* hdr = (double*)(prep + l.hdr);
+  double* d_b = (double*)(prep + l.d_b);
+  const double* out = (const double*)(prep + l.nout);
+  if (!normalize) { for (int i = 0; i < 8; ++i) hdr[i] = 0.0; return; }
+  // the network was evaluated at a single point, so out is [NOUT][1]
+  hdr[0] = out[0];
+  for (int q = 0; q < npair; ++q) {
+    const double kap = out[1 + 3 + q] + 2.0 * out[1 + 3 + npair + q];
+    hdr[1 + q] = kap;
+    d_b[3 + q] -= kap;
+  }
+}
+
+// ---------------------------------------------------------------- network kernel
+template <class E>
+__device__ inline const typename E::frag* frag_ptr(const unsigned char* prep, const PrepLayout& l, int which);
+
+template <>
+__device__ inline const double* frag_ptr<EngF64>(const unsigned char* prep, const PrepLayout& l, int which) {
+  return (const double*)(prep + (which == 0 ? l.x_W1 : which == 1 ? l.x_A : l.x_B));
+}
+template <>
+__device__ inline const float* frag_ptr<EngF32>(const unsigned char* prep, const PrepLayout& l, int which) {
+  return (const float*)(prep + (which == 0 ? l.y_W1 : which == 1 ? l.y_A : l.y_B));
+}
+template <>
+__device__ inline const bf16x8* frag_ptr<EngBF16>(const unsigned char* prep, const PrepLayout& l, int which) {
+  return (const bf16x8*)(prep + (which == 0 ? l.z_W1 : which == 1 ? l.z_A : l.z_B));
+}
+
+template <class E, int H>
+__device__ constexpr int steps_hidden() { return E::KS == 4 ? H / 4 : (H + 31) / 32; }
+template <class E, int P>
+__device__ constexpr int steps_input() { return E::KS == 4 ? (P + 3) / 4 : 1; }
+
+// acc += A (16 x H, this wave's rows) * src (H x 16), where src holds, for
+// every 16-row block mb, the lane's 4 values at rows 16mb + E::row(g, v).
+template <class E, int MB>
+__device__ inline typename E::acc mma_src(const typename E::frag* A, const typename E::T (&src)[MB][4],
+                                          typename E::acc c) {
+  if constexpr (E::KS == 4) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c = E::mma(A[mb * 4 + v], (typename E::frag)src[mb][v], c);
+  } else {
+#pragma unroll
+    for (int t = 0; t < (MB + 1) / 2; ++t) {
+      bf16x8 b;
+      const int t1 = (2 * t + 1 < MB) ? 2 * t + 1 : 2 * t;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[e] = (__bf16)src[2 * t][e];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[4 + e] = (2 * t + 1 < MB) ? (__bf16)src[t1][e] : (__bf16)0.0f;
+      c = E::mma(A[t], b, c);
+    }
+  }
+  return c;
+}
+
+// acc += Bk (16 x P) * K (P x 16) over the input features.
+template <class E, int P>
+__device__ inline typename E::acc mma_in(const typename E::frag* A, const typename E::frag* kB,
+                                         typename E::acc c) {
+#pragma unroll
+  for (int s = 0; s < steps_input<E, P>(); ++s) c = E::mma(A[s], kB[s], c);
+  return c;
+}
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1, so
+// every register-array index inside the body is a constant.
+template <class F, int... Is>
+__device__ inline void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ inline void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+__device__ constexpr int hess_m(int h, int P) {
+  int c = 0;
+  for (int m = 0; m < P; ++m)
+    for (int n = m; n < P; ++n) {
+      if (c == h) return m;
+      ++c;
+    }
+  return 0;
+}
+__device__ constexpr int hess_n(int h, int P) {
+  int c = 0;
+  for (int m = 0; m < P; ++m)
+    for (int n = m; n < P; ++n) {
+      if (c == h) return n;
+      ++c;
+    }
+  return 0;
+}
+
+template <class E> __device__ inline typename E::acc zero_acc() { return typename E::acc{0, 0, 0, 0}; }
+
+// Sum a per-lane partial over the four lane groups (rows) of the wave.
+__device__ inline double group_sum(double x) {
+  x += __shfl_xor(x, 16);
+  x += __shfl_xor(x, 32);
+  return x;
+}
+
+template <int H, int L, int P, int PR>
+struct MlpCfg {
+  using EV = typename std::conditional<PR == PREC_F64, EngF64,
+             typename std::conditional<PR == PREC_F32 || PR == PREC_BF16C, EngF32, EngBF16>::type>::type;
+  using EH = typename std::conditional<PR == PREC_F64, EngF64,
+             typename std::conditional<PR == PREC_F32, EngF32, EngBF16>::type>::type;
+  using T = typename EV::T;
+  static constexpr int MB = H / 16;
+  static constexpr int NW = MB;
+  static constexpr int P2 = P * (P + 1) / 2;
+  static constexpr int NOUT = 1 + P + P2;
+  static constexpr int CH = (L >= 3) ? 4 : 1;  // columns per LDS exchange chunk
+};
+
+template <int H, int L, int P, int PR>
+__global__ void __launch_bounds__(64 * (H / 16))
+k_mlp_fwd(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
+          const double* __restrict__ Kin, double* __restrict__ out) {
+  using C = MlpCfg<H, L, P, PR>;
+  using EV = typename C::EV;
+  using EH = typename C::EH;
+  using T = typename C::T;
+  constexpr int MB = C::MB, NW = C::NW, P2 = C::P2, NOUT = C::NOUT, CH = C::CH;
+  constexpr int SHV = steps_hidden<EV, H>();
+  constexpr int SHH = steps_hidden<EH, H>();
+  constexpr int S1V = steps_input<EV, P>();
+  constexpr bool SPLIT = !std::is_same<EV, EH>::value;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
+  const int64_t base = (int64_t)blockIdx.x * 16;
+  const int64_t qp = base + q;
+  const bool valid = qp < n;
+
+  __shared__ T W1s[P][H];
+  __shared__ double outp[NW][NOUT][16];
+  __shared__ T xbuf[CH][H][16];
+
+  const T* t_W1t = (const T*)(prep + (std::is_same<T, double>::value ? lay.d_W1t : lay.f_W1t));
+  const T* t_a = (const T*)(prep + (std::is_same<T, double>::value ? lay.d_a : lay.f_a));
+  const T* t_c = (const T*)(prep + (std::is_same<T, double>::value ? lay.d_c : lay.f_c));
+  const T* t_Bt = (const T*)(prep + (std::is_same<T, double>::value ? lay.d_Bt : lay.f_Bt));
+  const double* d_b = (const double*)(prep + lay.d_b);
+
+  for (int i = tid; i < P * H; i += 64 * NW) W1s[i / H][i % H] = t_W1t[i];
+
+  // ---- input features as B operands of the value engine
+  typename EV::frag kB[S1V];
+  if constexpr (EV::KS == 4) {
+#pragma unroll
+    for (int s = 0; s < S1V; ++s) {
+      const int m = 4 * s + g;
+      kB[s] = (valid && m < P) ? (T)Kin[(int64_t)m * n + qp] : (T)0;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int m = 8 * g + e;
+      kB[0][e] = (__bf16)(float)((valid && m < P) ? Kin[(int64_t)m * n + qp] : 0.0);
+    }
+  }
+
+  // ---- layer 1, all rows: y1 = W1 K + c1
+  T s1[MB][4], t1[MB][4], z1[MB][4];
+  {
+    const typename EV::frag* fW1 = frag_ptr<EV>(prep, lay, 0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      typename EV::frag a1[S1V];
+#pragma unroll
+      for (int s = 0; s < S1V; ++s) a1[s] = fW1[(mb * S1V + s) * 64 + lane];
+      typename EV::acc acc = mma_in<EV, P>(a1, kB, zero_acc<EV>());
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * mb + EV::row(g, v);
+        const T y = acc[v] + t_c[r];
+        T f, f1, f2;
+        softplus3(y, f, f1, f2);
+        z1[mb][v] = f; s1[mb][v] = f1; t1[mb][v] = f2;
+      }
+    }
+  }
+
+  // ---- weights of layers 2..L for this wave's rows (registers)
+  typename EV::frag AV[L - 1][SHV];
+  typename EV::frag BV[L - 1][S1V];
+  {
+    const typename EV::frag* fA = frag_ptr<EV>(prep, lay, 1);
+    const typename EV::frag* fB = frag_ptr<EV>(prep, lay, 2);
+#pragma unroll
+    for (int k = 2; k <= L; ++k) {
+#pragma unroll
+      for (int s = 0; s < SHV; ++s) AV[k - 2][s] = fA[(((k - 1) * MB + w) * SHV + s) * 64 + lane];
+#pragma unroll
+      for (int s = 0; s < S1V; ++s) BV[k - 2][s] = fB[(((k - 1) * MB + w) * S1V + s) * 64 + lane];
+    }
+  }
+  T a_own[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) a_own[v] = t_a[16 * w + EV::row(g, v)];
+
+  // stash of layers 2..L (own rows): F'(y), F''(y), dy/dK_m
+  T sk[L - 1][4], tk[L - 1][4], dyk[L - 1][P][4];
+
+  __syncthreads();  // W1s ready
+
+  auto emit = [&](int col, const T (&o)[4], const T (&aw)[4]) {
+    double pl = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pl += (double)(aw[v] * o[v]);
+    pl = group_sum(pl);
+    if (g == 0) outp[w][col][q] = pl;
+  };
+
+  // ================= value column
+  {
+    T src[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) src[mb][v] = z1[mb][v];
+    static_for<L - 1>([&](auto KI) {
+      constexpr int k = decltype(KI)::value + 2;
+      if constexpr (k >= 3) {
+        // gather all rows of layer k-1 from LDS
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) src[mb][v] = xbuf[0][16 * mb + EV::row(g, v)][q];
+        __syncthreads();
+      }
+      typename EV::acc acc = mma_src<EV, MB>(AV[k - 2], src, zero_acc<EV>());
+      acc = mma_in<EV, P>(BV[k - 2], kB, acc);
+      T o[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * w + EV::row(g, v);
+        const T y = acc[v] + t_c[(k - 1) * H + r];
+        T f, f1, f2;
+        softplus3(y, f, f1, f2);
+        sk[k - 2][v] = f1; tk[k - 2][v] = f2; o[v] = f;
+      }
+      if constexpr (k < L) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xbuf[0][16 * w + EV::row(g, v)][q] = o[v];
+      } else {
+        emit(0, o, a_own);
+      }
+    });
+  }
+
+  // ================= gradient columns dz/dK_m
+  constexpr int NGC = (P + CH - 1) / CH;
+  static_for<NGC>([&](auto CI) {
+    constexpr int c0 = decltype(CI)::value * CH;
+    T o[CH][4];
+    static_for<CH>([&](auto JI) {
+      constexpr int j = decltype(JI)::value;
+      constexpr int m = c0 + j;
+      if constexpr (m < P) {
+        T src[MB][4];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) src[mb][v] = s1[mb][v] * W1s[m][16 * mb + EV::row(g, v)];
+        typename EV::acc acc = mma_src<EV, MB>(AV[0], src, zero_acc<EV>());
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * w + EV::row(g, v);
+          const T d = acc[v] + t_Bt[((int64_t)1 * P + m) * H + r];
+          dyk[0][m][v] = d;
+          o[j][v] = sk[0][v] * d;
+        }
+      }
+    });
+    if constexpr (L == 2) {
+      static_for<CH>([&](auto JI) {
+        constexpr int j = decltype(JI)::value;
+        if constexpr (c0 + j < P) emit(1 + c0 + j, o[j], a_own);
+      });
+    } else {
+      static_for<CH>([&](auto JI) {
+        constexpr int j = decltype(JI)::value;
+        if constexpr (c0 + j < P) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) xbuf[j][16 * w + EV::row(g, v)][q] = o[j][v];
+        }
+      });
+      __syncthreads();
+      static_for<CH>([&](auto JI) {
+        constexpr int j = decltype(JI)::value;
+        constexpr int m = c0 + j;
+        if constexpr (m < P) {
+          T src[MB][4];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) src[mb][v] = xbuf[j][16 * mb + EV::row(g, v)][q];
+          typename EV::acc acc = mma_src<EV, MB>(AV[1], src, zero_acc<EV>());
+          T oo[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * w + EV::row(g, v);
+            const T d = acc[v] + t_Bt[((int64_t)2 * P + m) * H + r];
+            dyk[1][m][v] = d;
+            oo[v] = sk[1][v] * d;
+          }
+          emit(1 + m, oo, a_own);
+        }
+      });
+      __syncthreads();
+    }
+  });
+
+  // ================= Hessian columns d2z/dK_m dK_n (m <= n)
+  // For the split precision mode the value/gradient stash was produced by the
+  // FP32 engine (rows 4g + v) and the BF16 engine uses the same row order.
+  typename EH::frag AH[L - 1][SHH];
+  if constexpr (SPLIT) {
+    const typename EH::frag* fA = frag_ptr<EH>(prep, lay, 1);
+#pragma unroll
+    for (int k = 2; k <= L; ++k)
+#pragma unroll
+      for (int s = 0; s < SHH; ++s) AH[k - 2][s] = fA[(((k - 1) * MB + w) * SHH + s) * 64 + lane];
+  }
+  auto AHk = [&](int k) -> const typename EH::frag* {
+    if constexpr (SPLIT) return AH[k - 2]; else return (const typename EH::frag*)AV[k - 2];
+  };
+
+  constexpr int NHC = (P2 + CH - 1) / CH;
+  static_for<NHC>([&](auto CI) {
+    constexpr int h0 = decltype(CI)::value * CH;
+    T o[CH][4];
+    static_for<CH>([&](auto JI) {
+      constexpr int j = decltype(JI)::value;
+      constexpr int h = h0 + j;
+      if constexpr (h < P2) {
+        constexpr int m = hess_m(h, P), nn = hess_n(h, P);
+        T src[MB][4];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * mb + EH::row(g, v);
+            src[mb][v] = t1[mb][v] * W1s[m][r] * W1s[nn][r];
+          }
+        typename EH::acc acc = mma_src<EH, MB>(AHk(2), src, zero_acc<EH>());
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          o[j][v] = sk[0][v] * (T)acc[v] + tk[0][v] * dyk[0][m][v] * dyk[0][nn][v];
+      }
+    });
+    if constexpr (L == 2) {
+      static_for<CH>([&](auto JI) {
+        constexpr int j = decltype(JI)::value;
+        if constexpr (h0 + j < P2) emit(1 + P + h0 + j, o[j], a_own);
+      });
+    } else {
+      static_for<CH>([&](auto JI) {
+        constexpr int j = decltype(JI)::value;
+        if constexpr (h0 + j < P2) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) xbuf[j][16 * w + EH::row(g, v)][q] = o[j][v];
+        }
+      });
+      __syncthreads();
+      static_for<CH>([&](auto JI) {
+        constexpr int j = decltype(JI)::value;
+        constexpr int h = h0 + j;
+        if constexpr (h < P2) {
+          constexpr int m = hess_m(h, P), nn = hess_n(h, P);
+          T src[MB][4];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) src[mb][v] = xbuf[j][16 * mb + EH::row(g, v)][q];
+          typename EH::acc acc = mma_src<EH, MB>(AHk(3), src, zero_acc<EH>());
+          T oo[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            oo[v] = sk[1][v] * (T)acc[v] + tk[1][v] * dyk[1][m][v] * dyk[1][nn][v];
+          emit(1 + P + h, oo, a_own);
+        }
+      });
+      __syncthreads();
+    }
+  });
+
+  // ================= cross-wave sum in fixed order, skip term b.K, store
+  __syncthreads();
+  for (int i = tid; i < NOUT * 16; i += 64 * NW) {
+    const int c = i / 16, qq = i % 16;
+    const int64_t pt = base + qq;
+    if (pt >= n) continue;
+    double v = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) v += outp[ww][c][qq];
+    if (c == 0) {
+      for (int m = 0; m < P; ++m) v += d_b[m] * Kin[(int64_t)m * n + pt];
+    } else if (c <= P) {
+      v += d_b[c - 1];
+    }
+    out[(int64_t)c * n + pt] = v;
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+template <int H, int L, int P>
+static int launch_mlp_t(const PrepLayout& lay, int prec, const unsigned char* prep, int64_t n,
+                        const double* K, double* out, hipStream_t s) {
+  const unsigned grid = (unsigned)((n + 15) / 16);
+  const unsigned block = 64 * (H / 16);
+  switch (prec) {
+    case PREC_F64: k_mlp_fwd<H, L, P, PREC_F64><<<grid, block, 0, s>>>(prep, lay, n, K, out); break;
+    case PREC_F32: k_mlp_fwd<H, L, P, PREC_F32><<<grid, block, 0, s>>>(prep, lay, n, K, out); break;
+    case PREC_BF16: k_mlp_fwd<H, L, P, PREC_BF16><<<grid, block, 0, s>>>(prep, lay, n, K, out); break;
+    case PREC_BF16C: k_mlp_fwd<H, L, P, PREC_BF16C><<<grid, block, 0, s>>>(prep, lay, n, K, out); break;
+    default: return -1;
+  }
+  return 0;
+}
+
+#define PA_MLP_CONFIGS(X) \
+  X(16, 2, 3) X(16, 2, 5) X(16, 2, 9) X(16, 3, 3) X(16, 3, 5) X(16, 3, 9) \
+  X(32, 2, 3) X(32, 2, 5) X(32, 2, 9) X(32, 3, 3) X(32, 3, 5) X(32, 3, 9) \
+  X(64, 2, 3) X(64, 2, 5) X(64, 2, 9) X(64, 3, 3) X(64, 3, 5) X(64, 3, 9)
+
+bool mlp_supported(int H, int L, int P) {
+#define PA_SUP(h, l, p) if (H == h && L == l && P == p) return true;
+  PA_MLP_CONFIGS(PA_SUP)
+#undef PA_SUP
+  return false;
+}
+
+int launch_mlp(const PrepLayout& lay, int prec, int algo, const unsigned char* prep, int64_t n,
+               const double* K, double* out, hipStream_t s) {
+  if (n == 0) return 0;
+  if (algo != 0) return -2;
+#define PA_DISPATCH(h, l, p) \
+  if (lay.H == h && lay.L == l && lay.P == p) return launch_mlp_t<h, l, p>(lay, prec, prep, n, K, out, s);
+  PA_MLP_CONFIGS(PA_DISPATCH)
+#undef PA_DISPATCH
+  return -2;
+}
+
+int launch_prepare(const PrepLayout& lay, const ThetaLayout& tl, const double* theta,
+                   unsigned char* prep, int normalize, int npair, hipStream_t s) {
+  k_prep_tables<<<64, 256, 0, s>>>(theta, tl, lay, prep);
+  k_prep_frags<<<256, 256, 0, s>>>(theta, tl, lay, prep);
+  if (normalize) {
+    int rc = launch_mlp(lay, PREC_F64, 0, prep, 1, (const double*)(prep + lay.k0),
+                        (double*)(prep + lay.nout), s);
+    if (rc) return rc;
+  }
+  k_prep_fold<<<1, 64, 0, s>>>(lay, prep, normalize, npair);
+  return 0;
+}
+
+}  // namespace pa

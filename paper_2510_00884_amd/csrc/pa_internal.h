@@ -1,0 +1,74 @@
+// Internal host/device interface of the library: prepared-parameter layout
+// and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "kinematics.h"
+
+namespace pa {
+
+// Byte offsets into the prepared-parameter buffer (one per model).
+//   hdr:   N0 (double), kappa[3] (double)
+//   d_*:   FP64 tables, f_*: FP32 tables
+//          a[H], c[L][H] (hidden biases, layer k at k-1), W1t[P][H] (W1
+//          transposed), Bt[L][P][H] (skip weights B_k transposed, k >= 2), b[P]
+//   x_*:   FP64 matrix-core fragments, y_*: FP32 fragments, z_*: BF16 fragments
+//          W1 [MB][S1][64], A [L][MB][SH][64], B [L][MB][S1][64]
+//          (bf16: [..][64][8] with SHB/1 K steps)
+//   k0, nout: scratch used to evaluate the network at K = 0 (normalisation)
+struct PrepLayout {
+  int32_t H, L, P, MB, S1, SH, SHB, NOUT;
+  int64_t hdr;
+  int64_t d_a, d_b, d_c, d_W1t, d_Bt;
+  int64_t f_a, f_c, f_W1t, f_Bt;
+  int64_t x_W1, x_A, x_B;
+  int64_t y_W1, y_A, y_B;
+  int64_t z_W1, z_A, z_B;
+  int64_t k0, nout;
+  int64_t total;
+};
+
+// Offsets into the FP64 parameter vector theta.
+struct ThetaLayout {
+  int32_t H, L, P, has_bias;
+  int64_t W1, c1;     // c1 < 0 when absent
+  int64_t A[4], B[4], c[4];  // per layer k (index k), k >= 2
+  int64_t a, b, total;
+};
+
+PrepLayout prep_layout(int H, int L, int P);
+ThetaLayout theta_layout(int H, int L, int P, int has_bias);
+
+// kinematics / chain (kin_chain.hip)
+int launch_invariants(int nsv, int64_t n, const double* F, const ModelConst& mc, double* I_raw,
+                      double* K, double* dKdF, int32_t* n_bad, hipStream_t s);
+int launch_features(int nsv, int64_t n, const double* F, const ModelConst& mc, double* K,
+                    int32_t* n_bad, hipStream_t s);
+int launch_chain(int nsv, int64_t n, const double* F, const double* Nout, const double* N0,
+                 const ModelConst& mc, double* psi, double* P, double* A, int32_t* n_bad, hipStream_t s);
+
+// network (mlp.hip)
+bool mlp_supported(int H, int L, int P);
+int launch_prepare(const PrepLayout& lay, const ThetaLayout& tl, const double* theta,
+                   unsigned char* prep, int normalize, int npair, hipStream_t s);
+int launch_mlp(const PrepLayout& lay, int prec, int algo, const unsigned char* prep, int64_t n,
+               const double* K, double* out, hipStream_t s);
+
+// elements and assembly (fe.hip)
+int launch_geometry(int nen, int64_t n_el, int64_t n_nodes, const double* X, const int32_t* conn,
+                    double* dNdX, double* w, int32_t* n_bad, hipStream_t s);
+int launch_gather_F(int nen, int nq, int64_t n_el, const int32_t* conn, const double* dNdX,
+                    const double* u, double* F, hipStream_t s);
+int launch_integrate(int nen, int nq, int64_t n_el, const double* dNdX, const double* w,
+                     const double* P, const double* A, double* r_e, double* K_e, hipStream_t s);
+int launch_csr_map(int nen, int64_t n_el, const int32_t* conn, const int64_t* row_ptr,
+                   const int32_t* col, int32_t* e2csr, hipStream_t s);
+int launch_assemble(int nen, int64_t e_begin, int64_t e_count, const int32_t* perm, int64_t n_el,
+                    const int32_t* conn, const int64_t* row_ptr, const int32_t* e2csr,
+                    const double* r_e, const double* K_e, double* r, double* vals, hipStream_t s);
+int launch_fill(double* x, int64_t n, double v, hipStream_t s);
+
+}  // namespace pa

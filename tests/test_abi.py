@@ -1,0 +1,122 @@
+"""The C-ABI library loads and exports every symbol include/pa.h declares;
+host-only entry points (sizes, CSR pattern, colouring, argument checks) are
+exercised on the CPU.  No GPU compute call is made here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import fe
+from paper_2510_00884_amd import _lib as L
+from paper_2510_00884_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pa.h")
+
+
+def header_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(pa_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libpa.so not built")
+    return L.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = header_symbols()
+    assert len(syms) >= 18
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(L.SIGNATURES), set(syms) ^ set(L.SIGNATURES)
+
+
+def _desc(n_sv=2, h=32, Ld=2, has_bias=1):
+    d = L.ModelDesc()
+    d.n_sv, d.width, d.n_hidden, d.has_bias = n_sv, h, Ld, has_bias
+    d.A[0][0] = 1.0
+    d.A[1][1] = 1.0
+    return d
+
+
+@pytest.mark.parametrize("n_sv,h,Ld,bias", [(0, 16, 2, 1), (1, 16, 2, 1), (2, 32, 2, 1), (2, 64, 3, 1), (0, 16, 3, 0)])
+def test_sizes_match_generators(lib, n_sv, h, Ld, bias):
+    d = _desc(n_sv, h, Ld, bias)
+    p = synth.num_inputs(n_sv)
+    assert lib.pa_num_inputs(C.byref(d)) == p
+    assert lib.pa_num_params(C.byref(d)) == synth.num_params(p, h, Ld, bool(bias))
+    assert lib.pa_supported(C.byref(d)) == 1
+    assert lib.pa_prepared_bytes(C.byref(d)) > 0
+
+
+def test_argument_errors_before_launch(lib):
+    d = _desc()
+    d.n_sv = 3
+    assert lib.pa_supported(C.byref(d)) == 0
+    assert lib.pa_prepare_params(C.byref(d), C.c_void_p(8), C.c_void_p(8), None) == L.PA_ERR_ARG
+    assert b"n_sv" in lib.pa_last_error()
+    d = _desc(h=48)
+    assert lib.pa_prepare_params(C.byref(d), C.c_void_p(8), C.c_void_p(8), None) == L.PA_ERR_UNSUPPORTED
+    d = _desc()
+    rc = lib.pa_energy_stress_tangent(C.byref(d), C.c_void_p(8), 0, -1, None, None, None, None, None, None, 0, None)
+    assert rc == L.PA_ERR_ARG
+    rc = lib.pa_energy_stress_tangent(C.byref(d), C.c_void_p(8), 7, 10, C.c_void_p(8), None, None, None, None, None, 0, None)
+    assert rc == L.PA_ERR_ARG
+    rc = lib.pa_energy_stress_tangent(C.byref(d), C.c_void_p(8), 0, 10, C.c_void_p(8), None, None, None, None, None, 0, None)
+    assert rc == L.PA_ERR_WORKSPACE
+    m = L.Mesh(1, 8, 9, 8, 8, 8, 8)
+    rc = lib.pa_element_residual_stiffness(C.byref(d), C.c_void_p(8), 0, C.byref(m), C.c_void_p(8), C.c_void_p(8),
+                                           None, None, None, 0, None)
+    assert rc == L.PA_ERR_ARG
+    assert lib.pa_status_string(L.PA_ERR_WORKSPACE) == b"workspace too small"
+
+
+@pytest.mark.parametrize("kind,n", [("hex8", 3), ("tet10", 2)])
+def test_csr_pattern_matches_oracle_assembly(lib, kind, n):
+    X, conn, _ = (synth.hex_mesh if kind == "hex8" else synth.tet10_mesh)(n)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    nen = conn.shape[1]
+    nnz = C.c_int64()
+    assert lib.pa_csr_pattern(nen, conn.shape[0], X.shape[0], conn.ctypes.data_as(C.c_void_p), None, None,
+                              C.byref(nnz)) == 0
+    row_ptr = np.empty(3 * X.shape[0] + 1, dtype=np.int64)
+    col = np.empty(nnz.value, dtype=np.int32)
+    assert lib.pa_csr_pattern(nen, conn.shape[0], X.shape[0], conn.ctypes.data_as(C.c_void_p),
+                              row_ptr.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p), C.byref(nnz)) == 0
+    # the oracle's assembled matrix with all-ones element blocks has exactly this pattern
+    nd = 3 * nen
+    _, K = fe.assemble(conn, np.zeros((conn.shape[0], nd)), np.ones((conn.shape[0], nd, nd)), X.shape[0])
+    np.testing.assert_array_equal(row_ptr, K.indptr)
+    np.testing.assert_array_equal(col, K.indices)
+
+
+def test_csr_pattern_c0_size(lib):
+    X, conn, _ = synth.hex_mesh(8)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    nnz = C.c_int64()
+    lib.pa_csr_pattern(8, conn.shape[0], X.shape[0], conn.ctypes.data_as(C.c_void_p), None, None, C.byref(nnz))
+    assert nnz.value == 140625  # 8^3 hex8 mesh: 2,187 dofs, 140,625 nonzeros
+
+
+@pytest.mark.parametrize("kind,n", [("hex8", 4), ("tet10", 2)])
+def test_greedy_colouring_is_valid(lib, kind, n):
+    X, conn, _ = (synth.hex_mesh if kind == "hex8" else synth.tet10_mesh)(n)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    colour = np.empty(conn.shape[0], dtype=np.int32)
+    nc = C.c_int32()
+    assert lib.pa_colour_elements(conn.shape[1], conn.shape[0], X.shape[0], conn.ctypes.data_as(C.c_void_p),
+                                  colour.ctypes.data_as(C.c_void_p), C.byref(nc)) == 0
+    assert colour.min() == 0 and colour.max() == nc.value - 1
+    for c in range(nc.value):
+        nodes = conn[colour == c].ravel()
+        assert np.unique(nodes).size == nodes.size
+    bad = conn.copy()
+    bad[0, 0] = X.shape[0]
+    assert lib.pa_colour_elements(bad.shape[1], bad.shape[0], X.shape[0], bad.ctypes.data_as(C.c_void_p),
+                                  colour.ctypes.data_as(C.c_void_p), C.byref(nc)) == L.PA_ERR_ARG

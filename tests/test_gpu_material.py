@@ -1,0 +1,114 @@
+"""GPU parity of the constitutive path (pa_invariants, pa_energy_stress_tangent)
+against the FP64 oracle, element by element, on seeded inputs spanning
+several 16-point tiles and a ragged tail.
+
+Tolerances (normwise relative error over the batch): FP64 path 1e-12;
+FP32 network 1e-5; BF16 network 2e-2 on P; BF16 with the FP32 correction
+pass 1e-4 on P."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import calib, ncm
+from paper_2510_00884_amd import synth
+from gpu_util import close, need_gpu, rel, say
+
+pytestmark = pytest.mark.gpu
+
+# (n_sv, width, hidden layers, normalize)
+CASES = [(1, 16, 2, True), (2, 32, 2, True), (2, 64, 3, True), (0, 16, 3, False), (2, 32, 3, False),
+         (1, 64, 2, True), (0, 32, 2, True)]
+
+
+def build(api, n_sv, h, L, normalize, seed=1, algorithm="forward"):
+    p = synth.num_inputs(n_sv)
+    theta = synth.micnn_params(p, h, L, seed=seed)
+    Av = synth.structural_vectors(n_sv)
+    gm = api.Model(theta, n_sv, h, L, A=Av, normalize=normalize, algorithm=algorithm)
+    om = ncm.model_from_theta(theta, p, h, L, Av, normalize=normalize)
+    return gm, om
+
+
+def unpack(out, n):
+    return (out["psi"].cpu().numpy(), out["P"].cpu().numpy().T.reshape(n, 3, 3),
+            out["A"].cpu().numpy().T.reshape(n, 3, 3, 3, 3))
+
+
+def test_invariants_and_features():
+    api = need_gpu()
+    for n_sv in (0, 1, 2):
+        say("invariants", n_sv)
+        gm, om = build(api, n_sv, 16, 2, False)
+        F = synth.sample_F(1037, seed=3)
+        I_raw, K, dK = api.invariants(gm, torch.tensor(F, device="cuda"))
+        inv = ncm.invariants(F, om.Avec)
+        ref = [inv["I1"], inv["I2"], inv["I3"], inv["J"]] + inv["I4"] + inv["I5"]
+        close(I_raw.cpu().numpy(), np.stack(ref), 1e-14, "I_raw.cpu().numpy()")
+        Kr, g = calib.feature_grads(F, om.Avec)
+        close(K.cpu().numpy().T, Kr, 1e-13, "K.cpu().numpy().T")
+        close(dK.cpu().numpy().transpose(2, 0, 1), g.reshape(F.shape[0], -1, 9), 1e-13, "dK.cpu().numpy().transpose(2")
+
+
+@pytest.mark.parametrize("n_sv,h,L,normalize", CASES)
+def test_energy_stress_tangent_fp64(n_sv, h, L, normalize):
+    api = need_gpu()
+    say("material fp64", n_sv, h, L, normalize)
+    gm, om = build(api, n_sv, h, L, normalize)
+    n = 1000  # 62 full tiles of 16 and a ragged tail of 8
+    F = synth.sample_F(n, seed=0)
+    out = api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec="fp64")
+    psi, P, A = unpack(out, n)
+    ref = ncm.stress_stiffness(F, om)
+    close(psi, ref["psi"], 1e-12, "psi")
+    close(P, ref["P"], 1e-12, "P")
+    close(A, ref["A"], 1e-12, "A")
+
+
+def test_single_point_and_reference_state():
+    api = need_gpu()
+    say("single point / identity")
+    gm, om = build(api, 2, 32, 2, True)
+    out = api.energy_stress_tangent(gm, torch.eye(3, dtype=torch.float64, device="cuda")[None])
+    psi, P, A = unpack(out, 1)
+    assert abs(psi[0]) < 1e-13 and np.abs(P).max() < 1e-13
+    ref = ncm.stress_stiffness(np.eye(3)[None], om)
+    close(A, ref["A"], 1e-12, "A")
+
+
+def test_empty_batch():
+    api = need_gpu()
+    gm, _ = build(api, 1, 16, 2, True)
+    out = api.energy_stress_tangent(gm, torch.empty((0, 3, 3), dtype=torch.float64, device="cuda"))
+    assert out["P"].shape == (9, 0)
+
+
+def test_inverted_points_are_counted():
+    api = need_gpu()
+    say("inverted points")
+    gm, om = build(api, 1, 16, 2, False)
+    F = synth.sample_F(40, seed=8)
+    F[::3, :, 0] *= -1
+    nb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), n_bad=nb)
+    assert int(nb.item()) == len(range(0, 40, 3))
+    psi, P, A = unpack(out, 40)
+    ref = ncm.stress_stiffness(F, om)
+    close(P, ref["P"], 1e-12, "P")
+    close(A, ref["A"], 1e-12, "A")
+
+
+@pytest.mark.parametrize("prec,tol_psi,tol_P,tol_A", [("fp32", 1e-5, 1e-5, 1e-5), ("bf16", 2e-2, 2e-2, 1e-1),
+                                                      ("bf16_corr", 1e-4, 1e-4, 1e-1)])
+@pytest.mark.parametrize("n_sv,h,L", [(2, 32, 2), (2, 64, 3)])
+def test_precision_ladder(prec, tol_psi, tol_P, tol_A, n_sv, h, L):
+    api = need_gpu()
+    say("precision", prec, n_sv, h, L)
+    gm, om = build(api, n_sv, h, L, True)
+    n = 2000
+    F = synth.sample_F(n, seed=5)
+    out = api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec=prec)
+    psi, P, A = unpack(out, n)
+    ref = ncm.stress_stiffness(F, om)
+    e = (rel(psi, ref["psi"]), rel(P, ref["P"]), rel(A, ref["A"]))
+    say("  errors psi/P/A", e)
+    assert e[0] < tol_psi and e[1] < tol_P and e[2] < tol_A
