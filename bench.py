@@ -39,16 +39,23 @@ def mlp_flops_per_point(h, L, p):
 
 
 def kernel_bytes(name, nen, nq, p):
-    """Algorithmic HBM bytes per element for the bandwidth-bound kernels."""
+    """Algorithmic HBM bytes per element for the bandwidth-bound kernels:
+    every input read once and every output written once (read-modify-write
+    counts twice)."""
     nd = 3 * nen
     nout = 1 + p + p * (p + 1) // 2
     per_qp = {"features": 72 + 8 * p, "chain": 72 + 8 * nout + 72 + 648, "gather_F": 8 * 3 * nen + 72}
     if name in per_qp:
         return nq * per_qp[name]
-    if name == "integrate":
-        return nq * (72 + 648 + 8) + nq * nen * 3 * 8 + 8 * nd * nd + 8 * nd
+    inputs = nq * (72 + 8 * (nout - 1) + 8) + nq * nen * 3 * 8   # F, network derivatives, w, dN/dX
+    if name == "chain_integrate":
+        return inputs + 8 * nd * nd + 8 * nd                     # K_e, r_e written
+    if name == "chain_integrate_scatter":
+        return inputs + 16 * nd * nd + 16 * nd + 4 * nen * nen   # CSR and r read-modify-write, CSR map
     if name == "assemble":
         return 24 * nd * nd + 24 * nd
+    if name == "fill":
+        return None
     return None
 
 
@@ -82,6 +89,8 @@ def main():
     ap.add_argument("--variants", default="fp32,bf16,bf16_corr",
                     help="other precisions timed after the headline run ('' for none)")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="elements in the oracle CPU sample (0: skip)")
+    ap.add_argument("--unfused", action="store_true",
+                    help="element tables + separate assembly instead of the fused per-colour build")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -110,7 +119,7 @@ def main():
     ut = torch.tensor(u, device="cuda").reshape(-1).contiguous()
     ws = torch.empty(mesh.workspace_bytes(model), dtype=torch.uint8, device="cuda")
     bufs = {}
-    api.tangent_build(model, mesh, ut, prec=args.prec, workspace=ws, bufs=bufs)
+    api.tangent_build(model, mesh, ut, prec=args.prec, workspace=ws, bufs=bufs, fused=not args.unfused)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     print(f"[bench] setup {t_setup:.1f} s: {mesh.n_el} elements, {mesh.n_el * mesh.nq} points, "
@@ -120,7 +129,7 @@ def main():
 
     def run(prec, steps, warmup, profile):
         for _ in range(warmup):
-            api.tangent_build(model, mesh, ut, prec=prec, workspace=ws, bufs=bufs)
+            api.tangent_build(model, mesh, ut, prec=prec, workspace=ws, bufs=bufs, fused=not args.unfused)
         torch.cuda.synchronize()
         if profile:
             lib.pa_profile_enable(1)
@@ -128,7 +137,7 @@ def main():
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(steps):
-            api.tangent_build(model, mesh, ut, prec=prec, workspace=ws, bufs=bufs)
+            api.tangent_build(model, mesh, ut, prec=prec, workspace=ws, bufs=bufs, fused=not args.unfused)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
@@ -166,6 +175,7 @@ def main():
         else:
             launches_per_step = kern[dom]["launches"] / args.steps
             b = kernel_bytes(dom, mesh.nen, mesh.nq, p) * mesh.n_el / launches_per_step
+            per_launch_s = kern[dom]["ms_total"] / kern[dom]["launches"] / 1e3
             ach = b / per_launch_s
             roof = {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                     "frac": ach / HBM_PEAK, "traffic": None, "kernel": dom}
@@ -202,6 +212,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"hex8 {n}^3 unit cube, orthotropic e1/e2 (9 inputs), MICNN 2x32 softplus, "
                                "one Newton tangent build: residual + tangent + coloured CSR assembly",
+                   "path": "element tables + assembly" if args.unfused else "fused per-colour build",
                    "elements": mesh.n_el, "points": n_qp, "dofs": 3 * mesh.n_nodes, "nnz": mesh.nnz,
                    "colours": mesh.n_colours, "precision": args.prec, "algorithm": args.algo},
         "elements_per_s": mesh.n_el / (ms / 1e3),

@@ -209,10 +209,20 @@ int pa_element_csr_map(const pa_mesh* mesh, const pa_csr* csr, int32_t* e2csr, v
 /* Coloured scatter-assembly (Alg. 1, global accumulation over node-major
  * dofs): for each colour, one launch adds r_e into r and K_e into vals
  * without atomics.  zero_first = 1 clears r and vals first.  r may be NULL
- * (then r_e is ignored); K_e may be NULL (then vals is untouched). */
+ * (then r_e is ignored); K_e may be NULL (then vals is untouched).
+ * r_e, K_e in the layout written by pa_element_residual_stiffness. */
 int pa_assemble_csr(const pa_mesh* mesh, const pa_colouring* colouring, const pa_csr* csr,
                     const double* r_e, const double* K_e, double* r, double* vals,
                     int32_t zero_first, void* stream);
+/* One Newton tangent build, fused: u -> F -> network -> element rows added
+ * straight into r [n_rows] and vals [nnz] colour by colour (no element
+ * tables in memory).  Same numbers as pa_element_residual_stiffness followed
+ * by pa_assemble_csr (up to summation order within an element).  Requires
+ * elements numbered colour by colour (colouring->elem_perm == NULL).  r or
+ * vals may be NULL.  workspace: pa_element_workspace_bytes(desc, mesh). */
+int pa_tangent_build(const pa_model_desc* desc, const void* prepared, int prec, const pa_mesh* mesh,
+                     const pa_colouring* colouring, const pa_csr* csr, const double* u, double* r,
+                     double* vals, int32_t* n_bad, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- adjoint */
 size_t pa_param_backward_workspace(const pa_model_desc* desc, int prec, int64_t n_qp);

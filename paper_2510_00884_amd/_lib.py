@@ -63,6 +63,7 @@ SIGNATURES = {
     "pa_colour_elements": (C.c_int, [I32, I64, I64, P, P, C.POINTER(I32)]),
     "pa_element_csr_map": (C.c_int, [PMESH, PCSR, P, P]),
     "pa_assemble_csr": (C.c_int, [PMESH, PCOL, PCSR, P, P, P, P, I32, P]),
+    "pa_tangent_build": (C.c_int, [PDESC, P, C.c_int, PMESH, PCOL, PCSR, P, P, P, P, P, SZ, P]),
     "pa_param_backward_workspace": (SZ, [PDESC, C.c_int, I64]),
     "pa_param_backward": (C.c_int, [PDESC, P, C.c_int, I64, P, P, P, P, SZ, P]),
     "pa_profile_enable": (C.c_int, [I32]),

@@ -196,14 +196,15 @@ class FEMesh:
 
 def element_residual_stiffness(model: Model, mesh: FEMesh, u, prec="fp64", stiffness=True, workspace=None,
                                r_e=None, K_e=None, n_bad=None):
-    """r_e (n_el, nd) and K_e (n_el, nd, nd) for the mesh's (colour-ordered) elements.
-    u: (n_nodes, 3) or (3 n_nodes,) displacement, dof = 3*node + i."""
+    """r_e (nd, n_el) and K_e (nd, nd, n_el), element index fastest, for the
+    mesh's (colour-ordered) elements.  u: (n_nodes, 3) or (3 n_nodes,)
+    displacement, dof = 3*node + i."""
     u = u.reshape(-1).contiguous()
     dev = u.device
     if r_e is None:
-        r_e = torch.empty((mesh.n_el, mesh.nd), dtype=torch.float64, device=dev)
+        r_e = torch.empty((mesh.nd, mesh.n_el), dtype=torch.float64, device=dev)
     if stiffness and K_e is None:
-        K_e = torch.empty((mesh.n_el, mesh.nd, mesh.nd), dtype=torch.float64, device=dev)
+        K_e = torch.empty((mesh.nd, mesh.nd, mesh.n_el), dtype=torch.float64, device=dev)
     nb = mesh.workspace_bytes(model)
     if workspace is None or workspace.numel() < nb:
         workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
@@ -226,13 +227,33 @@ def assemble_csr(mesh: FEMesh, r_e, K_e, r=None, vals=None, zero_first=True):
     return r, vals
 
 
-def tangent_build(model: Model, mesh: FEMesh, u, prec="fp64", workspace=None, bufs=None):
-    """One Newton tangent build: u -> (r, CSR values)."""
+def tangent_build(model: Model, mesh: FEMesh, u, prec="fp64", workspace=None, bufs=None, fused=True,
+                  n_bad=None):
+    """One Newton tangent build: u -> (r, CSR values).  fused=True runs
+    pa_tangent_build (element rows scattered straight into CSR); fused=False
+    runs pa_element_residual_stiffness then pa_assemble_csr."""
     bufs = bufs if bufs is not None else {}
-    r_e, K_e = element_residual_stiffness(model, mesh, u, prec, workspace=workspace,
-                                          r_e=bufs.get("r_e"), K_e=bufs.get("K_e"))
-    r, vals = assemble_csr(mesh, r_e, K_e, r=bufs.get("r"), vals=bufs.get("vals"))
-    bufs.update(r_e=r_e, K_e=K_e, r=r, vals=vals)
+    if not fused:
+        r_e, K_e = element_residual_stiffness(model, mesh, u, prec, workspace=workspace,
+                                              r_e=bufs.get("r_e"), K_e=bufs.get("K_e"), n_bad=n_bad)
+        r, vals = assemble_csr(mesh, r_e, K_e, r=bufs.get("r"), vals=bufs.get("vals"))
+        bufs.update(r_e=r_e, K_e=K_e, r=r, vals=vals)
+        return r, vals
+    u = u.reshape(-1).contiguous()
+    dev = u.device
+    r = bufs.get("r")
+    vals = bufs.get("vals")
+    if r is None:
+        r = torch.empty(3 * mesh.n_nodes, dtype=torch.float64, device=dev)
+    if vals is None:
+        vals = torch.empty(mesh.nnz, dtype=torch.float64, device=dev)
+    nb = mesh.workspace_bytes(model)
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+    L.check(model.lib.pa_tangent_build(C.byref(model.desc), _p(model.prepared), _prec(prec), C.byref(mesh.c_mesh),
+                                       C.byref(mesh.c_col), C.byref(mesh.c_csr), _p(u), _p(r), _p(vals), _p(n_bad),
+                                       _p(workspace), workspace.numel(), _stream()), "pa_tangent_build")
+    bufs.update(r=r, vals=vals)
     return r, vals
 
 

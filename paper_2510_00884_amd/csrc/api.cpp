@@ -255,9 +255,43 @@ int pa_mesh_geometry(int32_t nen, int64_t n_el, int64_t n_nodes, const double* X
 size_t pa_element_workspace_bytes(const pa_model_desc* d, const pa_mesh* m) {
   if (!d || !m || d->n_sv < 0 || d->n_sv > 2) return 0;
   const int64_t n = m->n_el * m->nq;
-  // F [9][n], P [9][n], AA [81][n], then the material workspace
-  return (size_t)(al(8 * 9 * n) * 2 + al(8 * 81 * n) + material_ws(d, n));
+  // F [9][n], then the material workspace (features, network derivatives)
+  return (size_t)(al(8 * 9 * n) + material_ws(d, n));
 }
+
+namespace {
+// u -> F -> features -> network derivatives (workspace), shared by the
+// element entry points.  Returns the network-output pointer.
+int element_front(const pa_model_desc* d, const void* prepared, int prec, const pa_mesh* m, const double* u,
+                  int32_t* n_bad, unsigned char* ws, hipStream_t s, double** F_out, double** N_out) {
+  const int64_t n = m->n_el * m->nq;
+  const int p = p_of(d);
+  double* F = (double*)ws;
+  unsigned char* mws = ws + al(8 * 9 * n);
+  double* K = (double*)mws;
+  double* Nout = (double*)(mws + al(8 * (int64_t)p * n));
+  const PrepLayout lay = layout_of(d);
+  const ModelConst mc = model_const(d);
+  {
+    Prof pr("gather_F", s);
+    launch_gather_F(m->nen, m->nq, m->n_el, m->conn, m->dNdX, u, F, s);
+  }
+  {
+    Prof pr("features", s);
+    launch_features(d->n_sv, n, F, mc, K, n_bad, s);
+  }
+  int rc;
+  {
+    Prof pr(d->algorithm == PA_ALGO_ADJOINT ? "mlp_adjoint" : "mlp_forward", s);
+    rc = launch_mlp(lay, prec, d->algorithm, (const unsigned char*)prepared, n, K, Nout, s);
+  }
+  if (rc == -2) return fail(PA_ERR_UNSUPPORTED, "network algorithm %d not available", d->algorithm);
+  if (rc) return fail(PA_ERR_ARG, "bad network configuration");
+  *F_out = F;
+  *N_out = Nout;
+  return PA_OK;
+}
+}  // namespace
 
 int pa_element_residual_stiffness(const pa_model_desc* d, const void* prepared, int prec, const pa_mesh* m,
                                   const double* u, double* r_e, double* K_e, int32_t* n_bad,
@@ -270,23 +304,54 @@ int pa_element_residual_stiffness(const pa_model_desc* d, const void* prepared, 
   if (!prepared || !u || !r_e) return fail(PA_ERR_ARG, "prepared, u and r_e must be non-NULL");
   const int64_t need = (int64_t)pa_element_workspace_bytes(d, m);
   if (!workspace || (int64_t)ws_bytes < need) return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
-  const int64_t n = m->n_el * m->nq;
-  unsigned char* ws = (unsigned char*)workspace;
-  double* F = (double*)ws;
-  double* P = (double*)(ws + al(8 * 9 * n));
-  double* A = (double*)(ws + 2 * al(8 * 9 * n));
-  unsigned char* mws = ws + 2 * al(8 * 9 * n) + al(8 * 81 * n);
   hipStream_t s = S(stream);
+  double *F, *Nout;
+  if ((rc = element_front(d, prepared, prec, m, u, n_bad, (unsigned char*)workspace, s, &F, &Nout))) return rc;
   {
-    Prof pr("gather_F", s);
-    launch_gather_F(m->nen, m->nq, m->n_el, m->conn, m->dNdX, u, F, s);
-  }
-  if ((rc = run_material(d, prepared, prec, n, F, nullptr, P, K_e ? A : nullptr, n_bad, mws, s))) return rc;
-  {
-    Prof pr("integrate", s);
-    launch_integrate(m->nen, m->nq, m->n_el, m->dNdX, m->w, P, A, r_e, K_e, s);
+    Prof pr("chain_integrate", s);
+    launch_chain_integrate(m->nen, d->n_sv, m->n_el, 0, m->n_el, m->conn, m->dNdX, m->w, F, Nout, model_const(d),
+                           r_e, K_e, nullptr, nullptr, nullptr, nullptr, false, s);
   }
   return hip_check("pa_element_residual_stiffness");
+}
+
+int pa_tangent_build(const pa_model_desc* d, const void* prepared, int prec, const pa_mesh* m,
+                     const pa_colouring* col, const pa_csr* c, const double* u, double* r, double* vals,
+                     int32_t* n_bad, void* workspace, size_t ws_bytes, void* stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_mesh(m))) return rc;
+  if (!col || !c) return fail(PA_ERR_ARG, "colouring and csr must be non-NULL");
+  if (col->elem_perm) return fail(PA_ERR_ARG, "pa_tangent_build needs elements numbered colour by colour (elem_perm = NULL)");
+  if (col->n_colours < 0 || (col->n_colours > 0 && !col->colour_ptr)) return fail(PA_ERR_ARG, "bad colouring");
+  if (col->n_colours > 0 && (col->colour_ptr[0] != 0 || col->colour_ptr[col->n_colours] != m->n_el))
+    return fail(PA_ERR_ARG, "colour_ptr must start at 0 and end at n_el");
+  for (int i = 0; i < col->n_colours; ++i)
+    if (col->colour_ptr[i + 1] < col->colour_ptr[i]) return fail(PA_ERR_ARG, "colour_ptr not monotone");
+  if (c->n_rows != 3 * m->n_nodes) return fail(PA_ERR_ARG, "csr has %lld rows, mesh needs %lld", (long long)c->n_rows, (long long)(3 * m->n_nodes));
+  if (vals && (!c->row_ptr || !c->e2csr)) return fail(PA_ERR_ARG, "csr row_ptr and e2csr needed for vals");
+  if (!r && !vals) return fail(PA_ERR_ARG, "nothing to assemble");
+  if (m->n_el == 0) return PA_OK;
+  if (!prepared || !u) return fail(PA_ERR_ARG, "prepared and u must be non-NULL");
+  const int64_t need = (int64_t)pa_element_workspace_bytes(d, m);
+  if (!workspace || (int64_t)ws_bytes < need) return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
+  hipStream_t s = S(stream);
+  double *F, *Nout;
+  if ((rc = element_front(d, prepared, prec, m, u, n_bad, (unsigned char*)workspace, s, &F, &Nout))) return rc;
+  {
+    Prof pr("fill", s);
+    if (r) launch_fill(r, c->n_rows, 0.0, s);
+    if (vals) launch_fill(vals, c->nnz, 0.0, s);
+  }
+  const ModelConst mc = model_const(d);
+  for (int k = 0; k < col->n_colours; ++k) {
+    Prof pr("chain_integrate_scatter", s);
+    const int64_t b = col->colour_ptr[k], cnt = col->colour_ptr[k + 1] - b;
+    launch_chain_integrate(m->nen, d->n_sv, m->n_el, b, cnt, m->conn, m->dNdX, m->w, F, Nout, mc, nullptr,
+                           nullptr, c->row_ptr, c->e2csr, r, vals, true, s);
+  }
+  return hip_check("pa_tangent_build");
 }
 
 int pa_csr_pattern(int32_t nen, int64_t n_el, int64_t n_nodes, const int32_t* conn_host, int64_t* row_ptr,

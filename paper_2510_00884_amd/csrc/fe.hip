@@ -48,7 +48,7 @@ __device__ inline void ref_grads<10>(int q, double (&dN)[10][3], double& wq) {
 }
 
 template <int NEN>
-__device__ inline constexpr int nq_of() { return NEN == 8 ? 8 : 4; }
+__host__ __device__ inline constexpr int nq_of() { return NEN == 8 ? 8 : 4; }
 
 // ---------------------------------------------------------------- geometry
 template <int NEN>
@@ -127,72 +127,137 @@ __global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, const int32_t* _
   for (int c = 0; c < 9; ++c) F[(int64_t)c * n + t] = f[c];
 }
 
-// ---------------------------------------------------------------- integration
-// One thread per (element, node a): rows 3a..3a+2 of K_e and r_e.
-//   r^a_i  = sum_q w P_iJ dN^a/dX_J
-//   K^ab_ik = sum_q w dN^a/dX_J AA_iJkL dN^b/dX_L
-template <int NEN>
-__global__ void __launch_bounds__(256) k_integrate(int64_t n_el, const double* __restrict__ dNdX,
-                                                   const double* __restrict__ w, const double* __restrict__ P,
-                                                   const double* __restrict__ A, double* __restrict__ r_e,
-                                                   double* __restrict__ K_e) {
+// ---------------------------------------------------------------- chain rule + integration
+// Fused kernel over a block of E elements (E * NQ = 128 points):
+//  phase A, one thread per point: kinematics and chain rule from the network
+//    derivatives -> F, S~ = dPsi/dC, CC~ = d2Psi/dCdC (tensor components) in LDS;
+//  phase B, one thread per (element, element row 3a+i):
+//    r^a_i      = sum_q w 2 (F S~ G^a)_i,                     G^a = dN^a/dX
+//    K^ab_ik    = sum_q w [2 delta_ik G^a.S~ G^b + 4 F_iI F_kK G^a_J CC~_IJKL G^b_L]
+//  i.e. the material form  sum_q w G^a_J AA_iJkL G^b_L  with AA never stored.
+// SCATTER = false writes r_e [nd][n_el] and K_e [nd][nd][n_el];
+// SCATTER = true adds the rows straight into the global r and CSR values
+// (one launch per colour, so no two threads touch the same entry).
+template <int NEN, int NSV, bool SCATTER>
+__global__ void __launch_bounds__(128) k_chain_integrate(
+    int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* __restrict__ conn,
+    const double* __restrict__ dNdX, const double* __restrict__ w, const double* __restrict__ F,
+    const double* __restrict__ Nout, ModelConst mc, double* __restrict__ r_e, double* __restrict__ K_e,
+    const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ e2csr, double* __restrict__ r,
+    double* __restrict__ vals) {
   constexpr int NQ = nq_of<NEN>();
   constexpr int ND = 3 * NEN;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_el * NEN) return;
-  const int64_t e = t / NEN;
-  const int a = (int)(t % NEN);
+  constexpr int NT = 128;
+  constexpr int E = NT / NQ;  // elements per block
+  constexpr int P = Feat<NSV>::P;
+  __shared__ double sF[9][NT], sS[6][NT], sC[21][NT], sW[NT];
+  const int tid = threadIdx.x;
+  const int64_t eb = e_begin + (int64_t)blockIdx.x * E;
   const int64_t n = n_el * NQ;
-  double r[3] = {0, 0, 0};
-  double K[3][ND];
+  {  // phase A: point (q, le)
+    const int le = tid % E, q = tid / E;
+    const int64_t e = eb + le;
+    if (e < e_begin + e_count) {
+      const int64_t pt = (int64_t)q * n_el + e;
+      double f[9];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+      for (int c = 0; c < 9; ++c) f[c] = F[(int64_t)c * n + pt];
+      Kin k;
+      kin_compute<NSV>(f, mc, k);
+      auto N1 = [&](int m) { return Nout[(int64_t)(1 + m) * n + pt]; };
+      auto N2 = [&](int i) { return Nout[(int64_t)(1 + P + i) * n + pt]; };
+      double S[6], CCt[21];
+      chain_material_lean<NSV>(k, mc, N1, N2, S, CCt);
 #pragma unroll
-    for (int c = 0; c < ND; ++c) K[i][c] = 0.0;
-  for (int q = 0; q < NQ; ++q) {
-    const int64_t pt = (int64_t)q * n_el + e;
-    const double wq = w[pt];
-    double ga[3];
+      for (int c = 0; c < 9; ++c) sF[c][tid] = f[c];
 #pragma unroll
-    for (int J = 0; J < 3; ++J) ga[J] = dNdX[(((int64_t)q * NEN + a) * 3 + J) * n_el + e];
+      for (int c = 0; c < 6; ++c) sS[c][tid] = S[c];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      double s = 0.0;
-#pragma unroll
-      for (int J = 0; J < 3; ++J) s += P[(int64_t)(3 * i + J) * n + pt] * ga[J];
-      r[i] += wq * s;
+      for (int c = 0; c < 21; ++c) sC[c][tid] = CCt[c];
+      sW[tid] = w[pt];
     }
-    // T_ikL = sum_J ga_J AA_iJkL
-    double T[3][3][3];
+  }
+  __syncthreads();
+  // phase B: (element le, row rho = 3a + i), element fastest
+  for (int idx = tid; idx < E * ND; idx += NT) {
+    const int le = idx % E, rho = idx / E;
+    const int a = rho / 3, i = rho % 3;
+    const int64_t e = eb + le;
+    if (e >= e_begin + e_count) continue;
+    double acc[ND];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int c = 0; c < ND; ++c) acc[c] = 0.0;
+    double rr = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < NQ; ++q) {
+      const int lq = q * E + le;
+      double ga[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
+      for (int J = 0; J < 3; ++J) ga[J] = dNdX[(((int64_t)q * NEN + a) * 3 + J) * n_el + e];
+      const double wq = sW[lq];
+      double Fi[3];  // row i of F
+#pragma unroll
+      for (int I = 0; I < 3; ++I) Fi[I] = sF[3 * i + I][lq];
+      double Sg[3];  // S~ G^a
+#pragma unroll
+      for (int I = 0; I < 3; ++I) Sg[I] = sS[VI(I, 0)][lq] * ga[0] + sS[VI(I, 1)][lq] * ga[1] + sS[VI(I, 2)][lq] * ga[2];
+      rr += wq * 2.0 * (Fi[0] * Sg[0] + Fi[1] * Sg[1] + Fi[2] * Sg[2]);
+      // Wv_KL = sum_I F_iI sum_J G^a_J CC~_IJKL   (row i only)
+      double Wv[3][3];
+#pragma unroll
+      for (int K = 0; K < 3; ++K)
 #pragma unroll
         for (int L = 0; L < 3; ++L) {
           double s = 0.0;
 #pragma unroll
-          for (int J = 0; J < 3; ++J) s += ga[J] * A[(int64_t)(9 * (3 * i + J) + 3 * k + L) * n + pt];
-          T[i][k][L] = wq * s;
+          for (int I = 0; I < 3; ++I) {
+            double v = 0.0;
+#pragma unroll
+            for (int J = 0; J < 3; ++J) v += ga[J] * sC[TRI(VI(I, J), VI(K, L))][lq];
+            s += Fi[I] * v;
+          }
+          Wv[K][L] = s;
+        }
+      // T_kL = 4 sum_K F_kK Wv_KL + 2 delta_ik (S~ G^a)_L, scaled by w
+      double T[3][3];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int L = 0; L < 3; ++L) {
+          double s = sF[3 * kk][lq] * Wv[0][L] + sF[3 * kk + 1][lq] * Wv[1][L] + sF[3 * kk + 2][lq] * Wv[2][L];
+          s = 4.0 * s + (kk == i ? 2.0 * Sg[L] : 0.0);
+          T[kk][L] = wq * s;
         }
 #pragma unroll
-    for (int b = 0; b < NEN; ++b) {
-      double gb[3];
+      for (int b = 0; b < NEN; ++b) {
+        const double g0 = dNdX[(((int64_t)q * NEN + b) * 3 + 0) * n_el + e];
+        const double g1 = dNdX[(((int64_t)q * NEN + b) * 3 + 1) * n_el + e];
+        const double g2 = dNdX[(((int64_t)q * NEN + b) * 3 + 2) * n_el + e];
 #pragma unroll
-      for (int L = 0; L < 3; ++L) gb[L] = dNdX[(((int64_t)q * NEN + b) * 3 + L) * n_el + e];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) K[i][3 * b + k] += T[i][k][0] * gb[0] + T[i][k][1] * gb[1] + T[i][k][2] * gb[2];
+        for (int kk = 0; kk < 3; ++kk) acc[3 * b + kk] += T[kk][0] * g0 + T[kk][1] * g1 + T[kk][2] * g2;
+      }
     }
-  }
+    if constexpr (!SCATTER) {
+      r_e[(int64_t)rho * n_el + e] = rr;
+      if (K_e) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) r_e[e * ND + 3 * a + i] = r[i];
-  if (K_e) {
+        for (int c = 0; c < ND; ++c) K_e[((int64_t)rho * ND + c) * n_el + e] = acc[c];
+      }
+    } else {
+      const int64_t R = 3 * (int64_t)conn[(int64_t)a * n_el + e] + i;
+      if (r) r[R] += rr;
+      if (vals) {
+        const int64_t base = row_ptr[R];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int c = 0; c < ND; ++c) K_e[(e * ND + 3 * a + i) * ND + c] = K[i][c];
+        for (int b = 0; b < NEN; ++b) {
+          const int32_t off = e2csr[(e * NEN + a) * NEN + b];
+          if (off < 0) continue;
+          vals[base + off] += acc[3 * b];
+          vals[base + off + 1] += acc[3 * b + 1];
+          vals[base + off + 2] += acc[3 * b + 2];
+        }
+      }
+    }
   }
 }
 
@@ -217,7 +282,8 @@ __global__ void __launch_bounds__(256) k_csr_map(int64_t n_el, const int32_t* __
 }
 
 // ---------------------------------------------------------------- assembly
-// One launch per colour; thread = (element of the colour, element row).
+// One launch per colour; thread = (element of the colour, element row),
+// element fastest so the SoA element tables are read coalesced.
 template <int NEN>
 __global__ void __launch_bounds__(256) k_assemble(int64_t e_begin, int64_t e_count, const int32_t* __restrict__ perm,
                                                   int64_t n_el, const int32_t* __restrict__ conn,
@@ -227,23 +293,22 @@ __global__ void __launch_bounds__(256) k_assemble(int64_t e_begin, int64_t e_cou
   constexpr int ND = 3 * NEN;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= e_count * ND) return;
-  const int64_t pos = e_begin + t / ND;
+  const int64_t pos = e_begin + t % e_count;
+  const int rho = (int)(t / e_count);
   const int64_t e = perm ? (int64_t)perm[pos] : pos;
-  const int rho = (int)(t % ND);
   const int a = rho / 3, i = rho % 3;
   const int64_t R = 3 * (int64_t)conn[(int64_t)a * n_el + e] + i;
-  if (r) r[R] += r_e[e * ND + rho];
+  if (r) r[R] += r_e[(int64_t)rho * n_el + e];
   if (vals) {
     const int64_t base = row_ptr[R];
-    const double* Krow = K_e + (e * ND + rho) * ND;
 #pragma unroll
     for (int b = 0; b < NEN; ++b) {
       const int32_t off = e2csr[(e * NEN + a) * NEN + b];
       if (off < 0) continue;  // column not in the pattern (cannot happen for a pattern built from conn)
       const int64_t p = base + off;
-      vals[p] += Krow[3 * b];
-      vals[p + 1] += Krow[3 * b + 1];
-      vals[p + 2] += Krow[3 * b + 2];
+      vals[p] += K_e[((int64_t)rho * ND + 3 * b) * n_el + e];
+      vals[p + 1] += K_e[((int64_t)rho * ND + 3 * b + 1) * n_el + e];
+      vals[p + 2] += K_e[((int64_t)rho * ND + 3 * b + 2) * n_el + e];
     }
   }
 }
@@ -277,12 +342,35 @@ int launch_gather_F(int nen, int nq, int64_t n_el, const int32_t* conn, const do
   return 0;
 }
 
-int launch_integrate(int nen, int nq, int64_t n_el, const double* dNdX, const double* w,
-                     const double* P, const double* A, double* r_e, double* K_e, hipStream_t s) {
-  if (n_el == 0) return 0;
-  (void)nq;
-  PA_NEN_SWITCH(nen, (k_integrate<8><<<nblocks(n_el * 8, 256), 256, 0, s>>>(n_el, dNdX, w, P, A, r_e, K_e)),
-                (k_integrate<10><<<nblocks(n_el * 10, 256), 256, 0, s>>>(n_el, dNdX, w, P, A, r_e, K_e)));
+template <int NEN, bool SC>
+static void launch_ci_t(int nsv, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
+                        const double* dNdX, const double* w, const double* F, const double* Nout,
+                        const ModelConst& mc, double* r_e, double* K_e, const int64_t* row_ptr,
+                        const int32_t* e2csr, double* r, double* vals, hipStream_t s) {
+  constexpr int E = 128 / nq_of<NEN>();
+  const unsigned grid = nblocks(e_count, E);
+  switch (nsv) {
+    case 0: k_chain_integrate<NEN, 0, SC><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals); break;
+    case 1: k_chain_integrate<NEN, 1, SC><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals); break;
+    default: k_chain_integrate<NEN, 2, SC><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals); break;
+  }
+}
+
+int launch_chain_integrate(int nen, int nsv, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
+                           const double* dNdX, const double* w, const double* F, const double* Nout,
+                           const ModelConst& mc, double* r_e, double* K_e, const int64_t* row_ptr,
+                           const int32_t* e2csr, double* r, double* vals, bool scatter, hipStream_t s) {
+  if (e_count == 0) return 0;
+  if (nsv < 0 || nsv > 2) return -1;
+  if (nen == 8) {
+    if (scatter) launch_ci_t<8, true>(nsv, n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals, s);
+    else launch_ci_t<8, false>(nsv, n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals, s);
+  } else if (nen == 10) {
+    if (scatter) launch_ci_t<10, true>(nsv, n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals, s);
+    else launch_ci_t<10, false>(nsv, n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals, s);
+  } else {
+    return -1;
+  }
   return 0;
 }
 

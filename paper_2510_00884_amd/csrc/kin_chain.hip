@@ -79,7 +79,6 @@ __global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restri
                                                double* __restrict__ Pout, double* __restrict__ Aout,
                                                int32_t* n_bad) {
   constexpr int P = Feat<NSV>::P;
-  constexpr int P2 = P * (P + 1) / 2;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   double f[9];
@@ -89,18 +88,11 @@ __global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restri
   kin_compute<NSV>(f, mc, k);
   if (psi) psi[t] = Nout[t] - N0[0];
   if (!Pout && !Aout) return;
-  double dN[P], d2N[P2];
-#pragma unroll
-  for (int m = 0; m < P; ++m) dN[m] = Nout[(1 + m) * n + t];
-  if (Aout) {
-#pragma unroll
-    for (int m = 0; m < P2; ++m) d2N[m] = Nout[(1 + P + m) * n + t];
-  } else {
-#pragma unroll
-    for (int m = 0; m < P2; ++m) d2N[m] = 0.0;
-  }
+  const bool second = Aout != nullptr;
+  auto N1 = [&](int m) { return Nout[(int64_t)(1 + m) * n + t]; };
+  auto N2 = [&](int i) { return second ? Nout[(int64_t)(1 + P + i) * n + t] : 0.0; };
   double S[6], CCt[21];
-  chain_material<NSV>(k, mc, dN, d2N, S, CCt);
+  chain_material_lean<NSV>(k, mc, N1, N2, S, CCt);
   push_material(
       k, S, CCt,
       [&](int c, double v) { if (Pout) Pout[(int64_t)c * n + t] = v; },

@@ -190,6 +190,10 @@ __host__ __device__ inline void slot_pair(int a, int& I, int& J) {
   J = tJ[a];
 }
 
+template <int NSV>
+__host__ __device__ inline void chain_first_order(const Kin& k, const ModelConst& mc, const double* dN,
+                                                  double* CCt);
+
 // Chain rule: given dN (p), d2N (p(p+1)/2 packed row-major upper), compute
 // S~ (6) and CC~ (21, upper triangle of the 6x6 in tensor components).
 template <int NSV>
@@ -224,6 +228,13 @@ __host__ __device__ inline void chain_material(const Kin& k, const ModelConst& m
 #pragma unroll
       for (int b = a; b < 6; ++b) CCt[TRI(a, b)] += D[m][a] * V[b];
   }
+  chain_first_order<NSV>(k, mc, dN, CCt);
+}
+
+// Adds sum_m N_m d2K_m/dCdC to CCt (upper triangle, tensor components).
+template <int NSV>
+__host__ __device__ inline void chain_first_order(const Kin& k, const ModelConst& mc, const double* dN,
+                                                  double* CCt) {
   // second derivatives of the features, weighted by N_m
   const double* c = k.c;
   constexpr int np = Feat<NSV>::NP;
@@ -298,6 +309,63 @@ __host__ __device__ inline void chain_material(const Kin& k, const ModelConst& m
       CCt[TRI(a, b)] += v;
     }
   }
+}
+
+// dK_m/dC for a feature index known only at run time (uniform across the
+// wave); every case is a compile-time instance, so nothing is indexed
+// dynamically in registers.
+template <int NSV>
+__host__ __device__ inline void kin_dfeature_rt(const Kin& k, const ModelConst& mc, int m, double* d) {
+  switch (m) {
+    case 0: kin_dfeature<NSV>(k, mc, 0, d); break;
+    case 1: kin_dfeature<NSV>(k, mc, 1, d); break;
+    case 2: kin_dfeature<NSV>(k, mc, 2, d); break;
+    case 3: if constexpr (Feat<NSV>::P > 3) kin_dfeature<NSV>(k, mc, 3, d); break;
+    case 4: if constexpr (Feat<NSV>::P > 4) kin_dfeature<NSV>(k, mc, 4, d); break;
+    case 5: if constexpr (Feat<NSV>::P > 5) kin_dfeature<NSV>(k, mc, 5, d); break;
+    case 6: if constexpr (Feat<NSV>::P > 6) kin_dfeature<NSV>(k, mc, 6, d); break;
+    case 7: if constexpr (Feat<NSV>::P > 7) kin_dfeature<NSV>(k, mc, 7, d); break;
+    default: if constexpr (Feat<NSV>::P > 8) kin_dfeature<NSV>(k, mc, 8, d); break;
+  }
+}
+
+// Same result as chain_material, with the network derivatives read through
+// accessors (N1(m) = dN/dK_m, N2(idx) = packed d2N) and the feature
+// gradients recomputed inside the loops instead of being held in registers.
+template <int NSV, class G1, class G2>
+__host__ __device__ inline void chain_material_lean(const Kin& k, const ModelConst& mc, G1 N1, G2 N2,
+                                                    double* S, double* CCt) {
+  constexpr int P = Feat<NSV>::P;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) S[a] = 0.0;
+#pragma unroll
+  for (int t = 0; t < 21; ++t) CCt[t] = 0.0;
+#pragma unroll 1
+  for (int m = 0; m < P; ++m) {
+    double Dm[6];
+    kin_dfeature_rt<NSV>(k, mc, m, Dm);
+    const double nm = N1(m);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) S[a] += nm * Dm[a];
+    double V[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int n = 0; n < P; ++n) {
+      double Dn[6];
+      kin_dfeature_rt<NSV>(k, mc, n, Dn);
+      const int mm = m < n ? m : n, nn = m < n ? n : m;
+      const double w = N2(mm * P - mm * (mm - 1) / 2 + (nn - mm));
+#pragma unroll
+      for (int a = 0; a < 6; ++a) V[a] += w * Dn[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = a; b < 6; ++b) CCt[TRI(a, b)] += Dm[a] * V[b];
+  }
+  double dN[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) dN[m] = N1(m);
+  chain_first_order<NSV>(k, mc, dN, CCt);
 }
 
 // P = 2 F S~ and AA_iJkL = 2 delta_ik S~_JL + 4 F_iI F_kK CC~_IJKL.

@@ -62,8 +62,10 @@ int launch_geometry(int nen, int64_t n_el, int64_t n_nodes, const double* X, con
                     double* dNdX, double* w, int32_t* n_bad, hipStream_t s);
 int launch_gather_F(int nen, int nq, int64_t n_el, const int32_t* conn, const double* dNdX,
                     const double* u, double* F, hipStream_t s);
-int launch_integrate(int nen, int nq, int64_t n_el, const double* dNdX, const double* w,
-                     const double* P, const double* A, double* r_e, double* K_e, hipStream_t s);
+int launch_chain_integrate(int nen, int nsv, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
+                           const double* dNdX, const double* w, const double* F, const double* Nout,
+                           const ModelConst& mc, double* r_e, double* K_e, const int64_t* row_ptr,
+                           const int32_t* e2csr, double* r, double* vals, bool scatter, hipStream_t s);
 int launch_csr_map(int nen, int64_t n_el, const int32_t* conn, const int64_t* row_ptr,
                    const int32_t* col, int32_t* e2csr, hipStream_t s);
 int launch_assemble(int nen, int64_t e_begin, int64_t e_count, const int32_t* perm, int64_t n_el,

@@ -53,14 +53,18 @@ def test_element_residual_stiffness_and_assembly(kind, n, n_sv, h, L):
     cperm = conn[mesh.perm]
     dNdX, w, _ = fe.geometry(X, cperm)
     r_ref, K_ref, _ = fe.element_residual_stiffness(u, cperm, dNdX, w, om)
-    close(r_e.cpu().numpy(), r_ref, 1e-12, "r_e.cpu().numpy()")
-    close(K_e.cpu().numpy(), K_ref, 1e-12, "K_e.cpu().numpy()")
+    close(r_e.cpu().numpy().T, r_ref, 1e-12, "r_e")
+    close(K_e.cpu().numpy().transpose(2, 0, 1), K_ref, 1e-12, "K_e")
     r, vals = api.assemble_csr(mesh, r_e, K_e)
     rg, Kg = fe.assemble(cperm, r_ref, K_ref, X.shape[0])
     np.testing.assert_array_equal(mesh.row_ptr_host, Kg.indptr)
     np.testing.assert_array_equal(mesh.col_host, Kg.indices)
     close(r.cpu().numpy(), rg, 1e-12, "r.cpu().numpy()")
     close(vals.cpu().numpy(), Kg.data, 1e-12, "vals.cpu().numpy()")
+    # fused build scatters the same rows straight into CSR
+    rf, vf = api.tangent_build(gm, mesh, ut, prec="fp64", fused=True)
+    close(rf.cpu().numpy(), rg, 1e-12, "fused r")
+    close(vf.cpu().numpy(), Kg.data, 1e-12, "fused vals")
 
 
 def test_assembly_greedy_colouring_and_determinism():
@@ -68,10 +72,14 @@ def test_assembly_greedy_colouring_and_determinism():
     say("assembly greedy colouring")
     X, conn, gm, om, mesh, u = setup(api, "hex8", 4, colour="greedy")
     ut = torch.tensor(u, device="cuda")
-    r1, v1 = api.tangent_build(gm, mesh, ut)
+    r1, v1 = api.tangent_build(gm, mesh, ut, fused=False)
     r1, v1 = r1.clone(), v1.clone()
-    r2, v2 = api.tangent_build(gm, mesh, ut)
+    r2, v2 = api.tangent_build(gm, mesh, ut, fused=False)
     assert torch.equal(r1, r2) and torch.equal(v1, v2)   # fixed colouring: bitwise deterministic
+    r3, v3 = api.tangent_build(gm, mesh, ut, fused=True)
+    r3, v3 = r3.clone(), v3.clone()
+    r4, v4 = api.tangent_build(gm, mesh, ut, fused=True)
+    assert torch.equal(r3, r4) and torch.equal(v3, v4)
     cperm = conn[mesh.perm]
     dNdX, w, _ = fe.geometry(X, cperm)
     r_ref, K_ref, _ = fe.element_residual_stiffness(u, cperm, dNdX, w, om)
@@ -88,6 +96,7 @@ def test_homogeneous_and_rigid_motion():
     u = X @ (Q - np.eye(3)).T + np.array([0.1, -0.2, 0.3])
     r_e, K_e = api.element_residual_stiffness(gm, mesh, torch.tensor(u, device="cuda"))
     assert r_e.abs().max().item() < 1e-12
+    K_e = K_e.permute(2, 0, 1)
     t = torch.tensor(np.tile([0.3, -1.1, 0.7], 8), device="cuda")
     assert (K_e @ t).abs().max().item() < 1e-11 * K_e.abs().max().item()
     assert (K_e - K_e.transpose(1, 2)).abs().max().item() < 1e-12 * K_e.abs().max().item()
