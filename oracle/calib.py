@@ -52,6 +52,12 @@ def _unpack_torch(theta, p, h, L, has_bias=True):
     return layers, a, b
 
 
+def _softplus(y):
+    """log(1 + e^y) in the overflow-free form max(y, 0) + log(1 + e^{-|y|});
+    exact for every y (no linearisation above a threshold)."""
+    return torch.clamp(y, min=0.0) + torch.log1p(torch.exp(-torch.abs(y)))
+
+
 def _network_value(K, layers, a, b):
     """eq. (icnn): y^k = A^k z^{k-1} + B^k z^0 + c^k, z^k = softplus(y^k),
     N = a . z^{L} + b . z^0."""
@@ -60,7 +66,7 @@ def _network_value(K, layers, a, b):
         y = z @ A.T + c
         if B is not None:
             y = y + K @ B.T
-        z = torch.nn.functional.softplus(y)
+        z = _softplus(y)
     return z @ a + K @ b
 
 

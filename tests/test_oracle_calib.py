@@ -48,3 +48,16 @@ def test_gradient_central_differences():
         e = np.zeros_like(theta); e[idx] = hstep
         fd = (calib.loss(theta + e, F, Pt, Av, p, h, L) - calib.loss(theta - e, F, Pt, Av, p, h, L)) / (2 * hstep)
         assert abs(fd - grad[idx]) <= 1e-6 * max(1.0, abs(grad).max())
+
+
+def test_gradient_large_preactivations_complex_step():
+    """3 x 64 network with non-negative weights: layer-3 pre-activations reach
+    the hundreds, where a linearised softplus would be off by e^{-y}; the
+    gradient still matches exact complex-step directional derivatives."""
+    theta, F, Pt, Av, p, h, L = setup(n=24, h=64, L=3)
+    Lval, grad = calib.loss_and_grad(theta, F, Pt, Av, p, h, L)
+    r = np.random.default_rng(3)
+    for _ in range(3):
+        v = r.normal(size=theta.shape)
+        d = np.imag(calib.loss(theta + 1j * 1e-20 * v, F, Pt, Av, p, h, L)) / 1e-20
+        assert abs(d - grad @ v) <= 1e-12 * max(1.0, abs(d))
