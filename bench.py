@@ -47,10 +47,12 @@ def kernel_bytes(name, nen, nq, p):
     per_qp = {"features": 72 + 8 * p, "chain": 72 + 8 * nout + 72 + 648, "gather_F": 8 * 3 * nen + 72}
     if name in per_qp:
         return nq * per_qp[name]
-    inputs = nq * (72 + 8 * (nout - 1) + 8) + nq * nen * 3 * 8   # F, network derivatives, w, dN/dX
-    if name == "chain_integrate":
+    if name == "material_cc":
+        return nq * (72 + 8 * (nout - 1) + 8 * 27)              # F, network derivatives in; S~, CC~ out
+    inputs = nq * (72 + 8 * 27 + 8) + nq * nen * 3 * 8           # F, S~ and CC~, w, dN/dX
+    if name == "integrate":
         return inputs + 8 * nd * nd + 8 * nd                     # K_e, r_e written
-    if name == "chain_integrate_scatter":
+    if name == "integrate_scatter":
         return inputs + 16 * nd * nd + 16 * nd + 4 * nen * nen   # CSR and r read-modify-write, CSR map
     if name == "assemble":
         return 24 * nd * nd + 24 * nd

@@ -14,7 +14,8 @@ import torch
 from . import _lib as L
 
 __all__ = ["Model", "FEMesh", "invariants", "energy_stress_tangent", "element_residual_stiffness",
-           "assemble_csr", "tangent_build", "param_backward", "num_params", "num_inputs"]
+           "assemble_csr", "tangent_build", "param_backward", "num_params", "num_inputs", "PaStress",
+           "stress"]
 
 
 def _p(t):
@@ -269,3 +270,33 @@ def param_backward(model: Model, F, P_bar, prec="fp32", soa=False, workspace=Non
     L.check(model.lib.pa_param_backward(C.byref(model.desc), _p(model.prepared), _prec(prec), n, _p(Fs), _p(Pb),
                                         _p(out), _p(workspace), workspace.numel(), _stream()), "pa_param_backward")
     return out
+
+
+class PaStress(torch.autograd.Function):
+    """P(theta, F) with the hand-written parameter adjoint as its backward.
+
+    forward: pa_energy_stress_tangent (stress only; no Hessian columns);
+    backward: pa_param_backward (activations recomputed, nothing stored but
+    theta and F).  Gradients flow to theta only."""
+
+    @staticmethod
+    def forward(ctx, theta, F, model, prec):
+        if theta.data_ptr() != model.theta.data_ptr() or not getattr(model, "_theta_current", False):
+            model.set_params(theta.detach())
+            model._theta_current = True
+        out = energy_stress_tangent(model, F, prec=prec, psi=False, P=True, A=False)
+        ctx.save_for_backward(theta, F)
+        ctx.model, ctx.prec = model, prec
+        return out["P"].t().reshape(-1, 3, 3)
+
+    @staticmethod
+    def backward(ctx, P_bar):
+        theta, F = ctx.saved_tensors
+        tb = param_backward(ctx.model, F, P_bar.contiguous(), prec=ctx.prec)
+        return tb.to(theta.dtype), None, None, None
+
+
+def stress(theta, F, model, prec="fp32"):
+    """Differentiable first Piola-Kirchhoff stress (n, 3, 3) of the raw network."""
+    model._theta_current = False
+    return PaStress.apply(theta, F, model, prec)

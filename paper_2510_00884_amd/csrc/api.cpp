@@ -144,7 +144,7 @@ int run_material(const pa_model_desc* d, const void* prepared, int prec, int64_t
   int rc;
   {
     Prof pr(d->algorithm == PA_ALGO_ADJOINT ? "mlp_adjoint" : "mlp_forward", s);
-    rc = launch_mlp(lay, prec, d->algorithm, prep, n, K, Nout, s);
+    rc = launch_mlp(lay, prec, d->algorithm, prep, n, K, Nout, A != nullptr, s);
   }
   if (rc == -2) return fail(PA_ERR_UNSUPPORTED, "network algorithm %d not available", d->algorithm);
   if (rc) return fail(PA_ERR_ARG, "bad network configuration");
@@ -255,19 +255,21 @@ int pa_mesh_geometry(int32_t nen, int64_t n_el, int64_t n_nodes, const double* X
 size_t pa_element_workspace_bytes(const pa_model_desc* d, const pa_mesh* m) {
   if (!d || !m || d->n_sv < 0 || d->n_sv > 2) return 0;
   const int64_t n = m->n_el * m->nq;
-  // F [9][n], then the material workspace (features, network derivatives)
-  return (size_t)(al(8 * 9 * n) + material_ws(d, n));
+  // F [9][n], S~ and CC~ [27][n], then the material workspace (features,
+  // network derivatives)
+  return (size_t)(al(8 * 9 * n) + al(8 * 27 * n) + material_ws(d, n));
 }
 
 namespace {
 // u -> F -> features -> network derivatives (workspace), shared by the
 // element entry points.  Returns the network-output pointer.
 int element_front(const pa_model_desc* d, const void* prepared, int prec, const pa_mesh* m, const double* u,
-                  int32_t* n_bad, unsigned char* ws, hipStream_t s, double** F_out, double** N_out) {
+                  int32_t* n_bad, unsigned char* ws, hipStream_t s, double** F_out, double** SC_out) {
   const int64_t n = m->n_el * m->nq;
   const int p = p_of(d);
   double* F = (double*)ws;
-  unsigned char* mws = ws + al(8 * 9 * n);
+  double* SC = (double*)(ws + al(8 * 9 * n));
+  unsigned char* mws = ws + al(8 * 9 * n) + al(8 * 27 * n);
   double* K = (double*)mws;
   double* Nout = (double*)(mws + al(8 * (int64_t)p * n));
   const PrepLayout lay = layout_of(d);
@@ -283,12 +285,16 @@ int element_front(const pa_model_desc* d, const void* prepared, int prec, const 
   int rc;
   {
     Prof pr(d->algorithm == PA_ALGO_ADJOINT ? "mlp_adjoint" : "mlp_forward", s);
-    rc = launch_mlp(lay, prec, d->algorithm, (const unsigned char*)prepared, n, K, Nout, s);
+    rc = launch_mlp(lay, prec, d->algorithm, (const unsigned char*)prepared, n, K, Nout, 1, s);
   }
   if (rc == -2) return fail(PA_ERR_UNSUPPORTED, "network algorithm %d not available", d->algorithm);
   if (rc) return fail(PA_ERR_ARG, "bad network configuration");
+  {
+    Prof pr("material_cc", s);
+    launch_material_cc(d->n_sv, n, F, Nout, mc, SC, s);
+  }
   *F_out = F;
-  *N_out = Nout;
+  *SC_out = SC;
   return PA_OK;
 }
 }  // namespace
@@ -305,12 +311,12 @@ int pa_element_residual_stiffness(const pa_model_desc* d, const void* prepared, 
   const int64_t need = (int64_t)pa_element_workspace_bytes(d, m);
   if (!workspace || (int64_t)ws_bytes < need) return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
   hipStream_t s = S(stream);
-  double *F, *Nout;
-  if ((rc = element_front(d, prepared, prec, m, u, n_bad, (unsigned char*)workspace, s, &F, &Nout))) return rc;
+  double *F, *SC;
+  if ((rc = element_front(d, prepared, prec, m, u, n_bad, (unsigned char*)workspace, s, &F, &SC))) return rc;
   {
-    Prof pr("chain_integrate", s);
-    launch_chain_integrate(m->nen, d->n_sv, m->n_el, 0, m->n_el, m->conn, m->dNdX, m->w, F, Nout, model_const(d),
-                           r_e, K_e, nullptr, nullptr, nullptr, nullptr, false, s);
+    Prof pr("integrate", s);
+    launch_chain_integrate(m->nen, m->n_el, 0, m->n_el, m->conn, m->dNdX, m->w, F, SC, r_e, K_e, nullptr,
+                           nullptr, nullptr, nullptr, false, s);
   }
   return hip_check("pa_element_residual_stiffness");
 }
@@ -337,19 +343,18 @@ int pa_tangent_build(const pa_model_desc* d, const void* prepared, int prec, con
   const int64_t need = (int64_t)pa_element_workspace_bytes(d, m);
   if (!workspace || (int64_t)ws_bytes < need) return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
   hipStream_t s = S(stream);
-  double *F, *Nout;
-  if ((rc = element_front(d, prepared, prec, m, u, n_bad, (unsigned char*)workspace, s, &F, &Nout))) return rc;
+  double *F, *SC;
+  if ((rc = element_front(d, prepared, prec, m, u, n_bad, (unsigned char*)workspace, s, &F, &SC))) return rc;
   {
     Prof pr("fill", s);
     if (r) launch_fill(r, c->n_rows, 0.0, s);
     if (vals) launch_fill(vals, c->nnz, 0.0, s);
   }
-  const ModelConst mc = model_const(d);
   for (int k = 0; k < col->n_colours; ++k) {
-    Prof pr("chain_integrate_scatter", s);
+    Prof pr("integrate_scatter", s);
     const int64_t b = col->colour_ptr[k], cnt = col->colour_ptr[k + 1] - b;
-    launch_chain_integrate(m->nen, d->n_sv, m->n_el, b, cnt, m->conn, m->dNdX, m->w, F, Nout, mc, nullptr,
-                           nullptr, c->row_ptr, c->e2csr, r, vals, true, s);
+    launch_chain_integrate(m->nen, m->n_el, b, cnt, m->conn, m->dNdX, m->w, F, SC, nullptr, nullptr, c->row_ptr,
+                           c->e2csr, r, vals, true, s);
   }
   return hip_check("pa_tangent_build");
 }
@@ -411,15 +416,31 @@ int pa_assemble_csr(const pa_mesh* m, const pa_colouring* col, const pa_csr* c, 
 }
 
 size_t pa_param_backward_workspace(const pa_model_desc* d, int prec, int64_t n) {
-  (void)d; (void)prec; (void)n;
-  return 0;
+  if (!d || d->n_sv < 0 || d->n_sv > 2 || n < 0 || d->width <= 0) return 0;
+  return (size_t)param_backward_ws(d->width, d->n_hidden, p_of(d), prec, n);
 }
 
 int pa_param_backward(const pa_model_desc* d, const void* prepared, int prec, int64_t n, const double* F,
                       const double* P_bar, double* theta_bar, void* workspace, size_t ws_bytes, void* stream) {
-  (void)d; (void)prepared; (void)prec; (void)n; (void)F; (void)P_bar; (void)theta_bar; (void)workspace;
-  (void)ws_bytes; (void)stream;
-  return fail(PA_ERR_UNSUPPORTED, "pa_param_backward not available yet");
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (prec != PA_FP64 && prec != PA_FP32) return fail(PA_ERR_UNSUPPORTED, "pa_param_backward supports PA_FP64 and PA_FP32");
+  if (d->normalize) return fail(PA_ERR_UNSUPPORTED, "pa_param_backward differentiates the raw network (normalize = 0)");
+  if (n < 0) return fail(PA_ERR_ARG, "n_qp < 0");
+  if (!prepared || !theta_bar || (n > 0 && (!F || !P_bar))) return fail(PA_ERR_ARG, "NULL argument");
+  const int64_t need = param_backward_ws(d->width, d->n_hidden, p_of(d), prec, n);
+  if (!workspace || (int64_t)ws_bytes < need) return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
+  const PrepLayout lay = layout_of(d);
+  const ThetaLayout tl = theta_layout(d->width, d->n_hidden, p_of(d), d->has_bias ? 1 : 0);
+  hipStream_t s = S(stream);
+  {
+    Prof pr("param_backward", s);
+    rc = launch_param_backward(lay, tl, d->n_sv, prec, (const unsigned char*)prepared, model_const(d), n, F, P_bar,
+                               theta_bar, (unsigned char*)workspace, s);
+  }
+  if (rc == -2) return fail(PA_ERR_UNSUPPORTED, "no adjoint kernel for this configuration");
+  if (rc) return fail(PA_ERR_ARG, "pa_param_backward failed (%d)", rc);
+  return hip_check("pa_param_backward");
 }
 
 int pa_profile_enable(int32_t on) {

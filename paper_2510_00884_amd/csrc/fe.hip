@@ -128,9 +128,9 @@ __global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, const int32_t* _
 }
 
 // ---------------------------------------------------------------- chain rule + integration
-// Fused kernel over a block of E elements (E * NQ = 128 points):
-//  phase A, one thread per point: kinematics and chain rule from the network
-//    derivatives -> F, S~ = dPsi/dC, CC~ = d2Psi/dCdC (tensor components) in LDS;
+// Element kernel over a block of E elements (E * NQ = 128 points):
+//  phase A, one thread per point: F, S~ = dPsi/dC, CC~ = d2Psi/dCdC (tensor
+//    components, formed per point by the material kernel) and w into LDS;
 //  phase B, one thread per (element, element row 3a+i):
 //    r^a_i      = sum_q w 2 (F S~ G^a)_i,                     G^a = dN^a/dX
 //    K^ab_ik    = sum_q w [2 delta_ik G^a.S~ G^b + 4 F_iI F_kK G^a_J CC~_IJKL G^b_L]
@@ -138,18 +138,17 @@ __global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, const int32_t* _
 // SCATTER = false writes r_e [nd][n_el] and K_e [nd][nd][n_el];
 // SCATTER = true adds the rows straight into the global r and CSR values
 // (one launch per colour, so no two threads touch the same entry).
-template <int NEN, int NSV, bool SCATTER>
+template <int NEN, bool SCATTER>
 __global__ void __launch_bounds__(128) k_chain_integrate(
     int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* __restrict__ conn,
     const double* __restrict__ dNdX, const double* __restrict__ w, const double* __restrict__ F,
-    const double* __restrict__ Nout, ModelConst mc, double* __restrict__ r_e, double* __restrict__ K_e,
+    const double* __restrict__ SC, double* __restrict__ r_e, double* __restrict__ K_e,
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ e2csr, double* __restrict__ r,
     double* __restrict__ vals) {
   constexpr int NQ = nq_of<NEN>();
   constexpr int ND = 3 * NEN;
   constexpr int NT = 128;
   constexpr int E = NT / NQ;  // elements per block
-  constexpr int P = Feat<NSV>::P;
   __shared__ double sF[9][NT], sS[6][NT], sC[21][NT], sW[NT];
   const int tid = threadIdx.x;
   const int64_t eb = e_begin + (int64_t)blockIdx.x * E;
@@ -159,21 +158,12 @@ __global__ void __launch_bounds__(128) k_chain_integrate(
     const int64_t e = eb + le;
     if (e < e_begin + e_count) {
       const int64_t pt = (int64_t)q * n_el + e;
-      double f[9];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) f[c] = F[(int64_t)c * n + pt];
-      Kin k;
-      kin_compute<NSV>(f, mc, k);
-      auto N1 = [&](int m) { return Nout[(int64_t)(1 + m) * n + pt]; };
-      auto N2 = [&](int i) { return Nout[(int64_t)(1 + P + i) * n + pt]; };
-      double S[6], CCt[21];
-      chain_material_lean<NSV>(k, mc, N1, N2, S, CCt);
+      for (int c = 0; c < 9; ++c) sF[c][tid] = F[(int64_t)c * n + pt];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) sF[c][tid] = f[c];
+      for (int c = 0; c < 6; ++c) sS[c][tid] = SC[(int64_t)c * n + pt];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) sS[c][tid] = S[c];
-#pragma unroll
-      for (int c = 0; c < 21; ++c) sC[c][tid] = CCt[c];
+      for (int c = 0; c < 21; ++c) sC[c][tid] = SC[(int64_t)(6 + c) * n + pt];
       sW[tid] = w[pt];
     }
   }
@@ -342,32 +332,19 @@ int launch_gather_F(int nen, int nq, int64_t n_el, const int32_t* conn, const do
   return 0;
 }
 
-template <int NEN, bool SC>
-static void launch_ci_t(int nsv, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
-                        const double* dNdX, const double* w, const double* F, const double* Nout,
-                        const ModelConst& mc, double* r_e, double* K_e, const int64_t* row_ptr,
-                        const int32_t* e2csr, double* r, double* vals, hipStream_t s) {
-  constexpr int E = 128 / nq_of<NEN>();
-  const unsigned grid = nblocks(e_count, E);
-  switch (nsv) {
-    case 0: k_chain_integrate<NEN, 0, SC><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals); break;
-    case 1: k_chain_integrate<NEN, 1, SC><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals); break;
-    default: k_chain_integrate<NEN, 2, SC><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals); break;
-  }
-}
-
-int launch_chain_integrate(int nen, int nsv, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
-                           const double* dNdX, const double* w, const double* F, const double* Nout,
-                           const ModelConst& mc, double* r_e, double* K_e, const int64_t* row_ptr,
-                           const int32_t* e2csr, double* r, double* vals, bool scatter, hipStream_t s) {
+int launch_chain_integrate(int nen, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
+                           const double* dNdX, const double* w, const double* F, const double* SC,
+                           double* r_e, double* K_e, const int64_t* row_ptr, const int32_t* e2csr, double* r,
+                           double* vals, bool scatter, hipStream_t s) {
   if (e_count == 0) return 0;
-  if (nsv < 0 || nsv > 2) return -1;
   if (nen == 8) {
-    if (scatter) launch_ci_t<8, true>(nsv, n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals, s);
-    else launch_ci_t<8, false>(nsv, n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals, s);
+    const unsigned grid = nblocks(e_count, 16);
+    if (scatter) k_chain_integrate<8, true><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e, row_ptr, e2csr, r, vals);
+    else k_chain_integrate<8, false><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e, row_ptr, e2csr, r, vals);
   } else if (nen == 10) {
-    if (scatter) launch_ci_t<10, true>(nsv, n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals, s);
-    else launch_ci_t<10, false>(nsv, n_el, e_begin, e_count, conn, dNdX, w, F, Nout, mc, r_e, K_e, row_ptr, e2csr, r, vals, s);
+    const unsigned grid = nblocks(e_count, 32);
+    if (scatter) k_chain_integrate<10, true><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e, row_ptr, e2csr, r, vals);
+    else k_chain_integrate<10, false><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e, row_ptr, e2csr, r, vals);
   } else {
     return -1;
   }

@@ -100,6 +100,36 @@ __global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restri
   (void)n_bad;
 }
 
+// dPsi/dC (6 slots) and d2Psi/dCdC (21 upper-triangle tensor components) per
+// point, SoA [27][n]: the material-form quantities the element kernels
+// integrate.  Fully unrolled: the network derivatives are loaded once and the
+// feature gradients stay in registers.
+template <int NSV>
+__global__ void __launch_bounds__(256) k_material_cc(int64_t n, const double* __restrict__ F,
+                                                     const double* __restrict__ Nout, ModelConst mc,
+                                                     double* __restrict__ SC) {
+  constexpr int P = Feat<NSV>::P;
+  constexpr int P2 = P * (P + 1) / 2;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double f[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = F[i * n + t];
+  Kin k;
+  kin_compute<NSV>(f, mc, k);
+  double dN[P], d2N[P2];
+#pragma unroll
+  for (int m = 0; m < P; ++m) dN[m] = Nout[(int64_t)(1 + m) * n + t];
+#pragma unroll
+  for (int m = 0; m < P2; ++m) d2N[m] = Nout[(int64_t)(1 + P + m) * n + t];
+  double S[6], CCt[21];
+  chain_material<NSV>(k, mc, dN, d2N, S, CCt);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) SC[(int64_t)c * n + t] = S[c];
+#pragma unroll
+  for (int c = 0; c < 21; ++c) SC[(int64_t)(6 + c) * n + t] = CCt[c];
+}
+
 // Features only (input to the network kernels).
 template <int NSV>
 __global__ void __launch_bounds__(256) k_features(int64_t n, const double* __restrict__ F, ModelConst mc,
@@ -142,6 +172,18 @@ int launch_features(int nsv, int64_t n, const double* F, const ModelConst& mc, d
     case 0: k_features<0><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, K, n_bad); break;
     case 1: k_features<1><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, K, n_bad); break;
     case 2: k_features<2><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, K, n_bad); break;
+    default: return -1;
+  }
+  return 0;
+}
+
+int launch_material_cc(int nsv, int64_t n, const double* F, const double* Nout, const ModelConst& mc,
+                       double* SC, hipStream_t s) {
+  if (n == 0) return 0;
+  switch (nsv) {
+    case 0: k_material_cc<0><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, mc, SC); break;
+    case 1: k_material_cc<1><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, mc, SC); break;
+    case 2: k_material_cc<2><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, mc, SC); break;
     default: return -1;
   }
   return 0;

@@ -25,6 +25,7 @@
 #include <utility>
 
 #include "pa_internal.h"
+#include "mma_util.h"
 
 namespace pa {
 
@@ -60,6 +61,8 @@ PrepLayout prep_layout(int H, int L, int P) {
   l.z_W1 = take(16 * (int64_t)l.MB * 64);
   l.z_A = take(16 * (int64_t)L * l.MB * l.SHB * 64);
   l.z_B = take(16 * (int64_t)L * l.MB * 64);
+  l.x_AT = take(8 * (int64_t)L * l.MB * l.SH * 64);
+  l.y_AT = take(4 * (int64_t)L * l.MB * l.SH * 64);
   l.k0 = take(8 * (int64_t)P * 16);
   l.nout = take(8 * (int64_t)l.NOUT * 16);
   l.total = o;
@@ -159,7 +162,10 @@ __global__ void k_prep_frags(const double* __restrict__ th, ThetaLayout t, PrepL
   const int64_t nzW1 = (int64_t)MB * 64 * 8;
   const int64_t nzA = (int64_t)L * MB * SHB * 64 * 8;
   const int64_t nzB = (int64_t)L * MB * 64 * 8;
-  const int64_t total = nW1 + nA + nB + nzW1 + nzA + nzB;
+  const int64_t nAT = (int64_t)L * MB * SH * 64;
+  double* xAT = (double*)(prep + l.x_AT);
+  float* yAT = (float*)(prep + l.y_AT);
+  const int64_t total = nW1 + nA + nB + nzW1 + nzA + nzB + nAT;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = idx;
     if (j < nW1) {  // [mb][s][lane]: W1[16mb + i][4s + g]
@@ -205,6 +211,15 @@ __global__ void k_prep_frags(const double* __restrict__ th, ThetaLayout t, PrepL
       continue;
     }
     j -= nzA;
+    if (j >= nzB) {  // [k-1][w][s][lane]: A_k[4s + g][16w + i] (reverse products)
+      j -= nzB;
+      const int lane = (int)(j % 64), s = (int)((j / 64) % SH);
+      const int w = (int)((j / (64 * SH)) % MB), k = (int)(j / (64 * SH * MB)) + 1;
+      const int i = lane & 15, g = lane >> 4;
+      const double v = (k >= 2) ? th_w(th, t, k, 4 * s + g, 16 * w + i) : 0.0;
+      xAT[j] = v; yAT[j] = (float)v;
+      continue;
+    }
     {  // [k-1][w][lane][e]: B_k[16w + i][8g + e]
       const int e = (int)(j % 8), lane = (int)((j / 8) % 64);
       const int w = (int)((j / 512) % MB), k = (int)(j / (512 * MB)) + 1;
@@ -232,100 +247,6 @@ __global__ void k_prep_fold(PrepLayout l, unsigned char* __restrict__ prep, int 
 }
 
 // ---------------------------------------------------------------- network kernel
-template <class E>
-__device__ inline const typename E::frag* frag_ptr(const unsigned char* prep, const PrepLayout& l, int which);
-
-template <>
-__device__ inline const double* frag_ptr<EngF64>(const unsigned char* prep, const PrepLayout& l, int which) {
-  return (const double*)(prep + (which == 0 ? l.x_W1 : which == 1 ? l.x_A : l.x_B));
-}
-template <>
-__device__ inline const float* frag_ptr<EngF32>(const unsigned char* prep, const PrepLayout& l, int which) {
-  return (const float*)(prep + (which == 0 ? l.y_W1 : which == 1 ? l.y_A : l.y_B));
-}
-template <>
-__device__ inline const bf16x8* frag_ptr<EngBF16>(const unsigned char* prep, const PrepLayout& l, int which) {
-  return (const bf16x8*)(prep + (which == 0 ? l.z_W1 : which == 1 ? l.z_A : l.z_B));
-}
-
-template <class E, int H>
-__device__ constexpr int steps_hidden() { return E::KS == 4 ? H / 4 : (H + 31) / 32; }
-template <class E, int P>
-__device__ constexpr int steps_input() { return E::KS == 4 ? (P + 3) / 4 : 1; }
-
-// acc += A (16 x H, this wave's rows) * src (H x 16), where src holds, for
-// every 16-row block mb, the lane's 4 values at rows 16mb + E::row(g, v).
-template <class E, int MB>
-__device__ inline typename E::acc mma_src(const typename E::frag* A, const typename E::T (&src)[MB][4],
-                                          typename E::acc c) {
-  if constexpr (E::KS == 4) {
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) c = E::mma(A[mb * 4 + v], (typename E::frag)src[mb][v], c);
-  } else {
-#pragma unroll
-    for (int t = 0; t < (MB + 1) / 2; ++t) {
-      bf16x8 b;
-      const int t1 = (2 * t + 1 < MB) ? 2 * t + 1 : 2 * t;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) b[e] = (__bf16)src[2 * t][e];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) b[4 + e] = (2 * t + 1 < MB) ? (__bf16)src[t1][e] : (__bf16)0.0f;
-      c = E::mma(A[t], b, c);
-    }
-  }
-  return c;
-}
-
-// acc += Bk (16 x P) * K (P x 16) over the input features.
-template <class E, int P>
-__device__ inline typename E::acc mma_in(const typename E::frag* A, const typename E::frag* kB,
-                                         typename E::acc c) {
-#pragma unroll
-  for (int s = 0; s < steps_input<E, P>(); ++s) c = E::mma(A[s], kB[s], c);
-  return c;
-}
-
-// Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1, so
-// every register-array index inside the body is a constant.
-template <class F, int... Is>
-__device__ inline void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
-  (f(std::integral_constant<int, Is>{}), ...);
-}
-template <int N, class F>
-__device__ inline void static_for(F&& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-__device__ constexpr int hess_m(int h, int P) {
-  int c = 0;
-  for (int m = 0; m < P; ++m)
-    for (int n = m; n < P; ++n) {
-      if (c == h) return m;
-      ++c;
-    }
-  return 0;
-}
-__device__ constexpr int hess_n(int h, int P) {
-  int c = 0;
-  for (int m = 0; m < P; ++m)
-    for (int n = m; n < P; ++n) {
-      if (c == h) return n;
-      ++c;
-    }
-  return 0;
-}
-
-template <class E> __device__ inline typename E::acc zero_acc() { return typename E::acc{0, 0, 0, 0}; }
-
-// Sum a per-lane partial over the four lane groups (rows) of the wave.
-__device__ inline double group_sum(double x) {
-  x += __shfl_xor(x, 16);
-  x += __shfl_xor(x, 32);
-  return x;
-}
-
 template <int H, int L, int P, int PR>
 struct MlpCfg {
   using EV = typename std::conditional<PR == PREC_F64, EngF64,
@@ -343,7 +264,7 @@ struct MlpCfg {
 template <int H, int L, int P, int PR>
 __global__ void __launch_bounds__(64 * (H / 16))
 k_mlp_fwd(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
-          const double* __restrict__ Kin, double* __restrict__ out) {
+          const double* __restrict__ Kin, double* __restrict__ out, int hess) {
   using C = MlpCfg<H, L, P, PR>;
   using EV = typename C::EV;
   using EH = typename C::EH;
@@ -541,6 +462,7 @@ k_mlp_fwd(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   });
 
   // ================= Hessian columns d2z/dK_m dK_n (m <= n)
+  if (hess) {
   // For the split precision mode the value/gradient stash was produced by the
   // FP32 engine (rows 4g + v) and the BF16 engine uses the same row order.
   typename EH::frag AH[L - 1][SHH];
@@ -614,9 +536,12 @@ k_mlp_fwd(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     }
   });
 
+  }  // hess
+
   // ================= cross-wave sum in fixed order, skip term b.K, store
   __syncthreads();
-  for (int i = tid; i < NOUT * 16; i += 64 * NW) {
+  const int nout_written = hess ? NOUT : 1 + P;
+  for (int i = tid; i < nout_written * 16; i += 64 * NW) {
     const int c = i / 16, qq = i % 16;
     const int64_t pt = base + qq;
     if (pt >= n) continue;
@@ -635,14 +560,14 @@ k_mlp_fwd(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 // ---------------------------------------------------------------- dispatch
 template <int H, int L, int P>
 static int launch_mlp_t(const PrepLayout& lay, int prec, const unsigned char* prep, int64_t n,
-                        const double* K, double* out, hipStream_t s) {
+                        const double* K, double* out, int hess, hipStream_t s) {
   const unsigned grid = (unsigned)((n + 15) / 16);
   const unsigned block = 64 * (H / 16);
   switch (prec) {
-    case PREC_F64: k_mlp_fwd<H, L, P, PREC_F64><<<grid, block, 0, s>>>(prep, lay, n, K, out); break;
-    case PREC_F32: k_mlp_fwd<H, L, P, PREC_F32><<<grid, block, 0, s>>>(prep, lay, n, K, out); break;
-    case PREC_BF16: k_mlp_fwd<H, L, P, PREC_BF16><<<grid, block, 0, s>>>(prep, lay, n, K, out); break;
-    case PREC_BF16C: k_mlp_fwd<H, L, P, PREC_BF16C><<<grid, block, 0, s>>>(prep, lay, n, K, out); break;
+    case PREC_F64: k_mlp_fwd<H, L, P, PREC_F64><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
+    case PREC_F32: k_mlp_fwd<H, L, P, PREC_F32><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
+    case PREC_BF16: k_mlp_fwd<H, L, P, PREC_BF16><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
+    case PREC_BF16C: k_mlp_fwd<H, L, P, PREC_BF16C><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
     default: return -1;
   }
   return 0;
@@ -661,11 +586,11 @@ bool mlp_supported(int H, int L, int P) {
 }
 
 int launch_mlp(const PrepLayout& lay, int prec, int algo, const unsigned char* prep, int64_t n,
-               const double* K, double* out, hipStream_t s) {
+               const double* K, double* out, int hess, hipStream_t s) {
   if (n == 0) return 0;
   if (algo != 0) return -2;
 #define PA_DISPATCH(h, l, p) \
-  if (lay.H == h && lay.L == l && lay.P == p) return launch_mlp_t<h, l, p>(lay, prec, prep, n, K, out, s);
+  if (lay.H == h && lay.L == l && lay.P == p) return launch_mlp_t<h, l, p>(lay, prec, prep, n, K, out, hess, s);
   PA_MLP_CONFIGS(PA_DISPATCH)
 #undef PA_DISPATCH
   return -2;
@@ -677,7 +602,7 @@ int launch_prepare(const PrepLayout& lay, const ThetaLayout& tl, const double* t
   k_prep_frags<<<256, 256, 0, s>>>(theta, tl, lay, prep);
   if (normalize) {
     int rc = launch_mlp(lay, PREC_F64, 0, prep, 1, (const double*)(prep + lay.k0),
-                        (double*)(prep + lay.nout), s);
+                        (double*)(prep + lay.nout), 1, s);
     if (rc) return rc;
   }
   k_prep_fold<<<1, 64, 0, s>>>(lay, prep, normalize, npair);

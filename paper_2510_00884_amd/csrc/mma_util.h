@@ -1,0 +1,130 @@
+// Matrix-core helpers shared by the network kernels: fragment access into
+// the prepared-parameter buffer, compile-time loops, K-step products with the
+// point tile on the N dimension, and cross-lane sums.
+#pragma once
+
+#include <type_traits>
+#include <utility>
+
+#include "pa_internal.h"
+
+namespace pa {
+template <class E>
+__device__ inline const typename E::frag* frag_ptr(const unsigned char* prep, const PrepLayout& l, int which);
+
+template <>
+__device__ inline const double* frag_ptr<EngF64>(const unsigned char* prep, const PrepLayout& l, int which) {
+  return (const double*)(prep + (which == 0 ? l.x_W1 : which == 1 ? l.x_A : l.x_B));
+}
+template <>
+__device__ inline const float* frag_ptr<EngF32>(const unsigned char* prep, const PrepLayout& l, int which) {
+  return (const float*)(prep + (which == 0 ? l.y_W1 : which == 1 ? l.y_A : l.y_B));
+}
+template <>
+__device__ inline const bf16x8* frag_ptr<EngBF16>(const unsigned char* prep, const PrepLayout& l, int which) {
+  return (const bf16x8*)(prep + (which == 0 ? l.z_W1 : which == 1 ? l.z_A : l.z_B));
+}
+
+template <class E, int H>
+__device__ constexpr int steps_hidden() { return E::KS == 4 ? H / 4 : (H + 31) / 32; }
+template <class E, int P>
+__device__ constexpr int steps_input() { return E::KS == 4 ? (P + 3) / 4 : 1; }
+
+// acc += A (16 x H, this wave's rows) * src (H x 16), where src holds, for
+// every 16-row block mb, the lane's 4 values at rows 16mb + E::row(g, v).
+template <class E, int MB>
+__device__ inline typename E::acc mma_src(const typename E::frag* A, const typename E::T (&src)[MB][4],
+                                          typename E::acc c) {
+  if constexpr (E::KS == 4) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c = E::mma(A[mb * 4 + v], (typename E::frag)src[mb][v], c);
+  } else {
+#pragma unroll
+    for (int t = 0; t < (MB + 1) / 2; ++t) {
+      bf16x8 b;
+      const int t1 = (2 * t + 1 < MB) ? 2 * t + 1 : 2 * t;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[e] = (__bf16)src[2 * t][e];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[4 + e] = (2 * t + 1 < MB) ? (__bf16)src[t1][e] : (__bf16)0.0f;
+      c = E::mma(A[t], b, c);
+    }
+  }
+  return c;
+}
+
+// acc += Bk (16 x P) * K (P x 16) over the input features.
+template <class E, int P>
+__device__ inline typename E::acc mma_in(const typename E::frag* A, const typename E::frag* kB,
+                                         typename E::acc c) {
+#pragma unroll
+  for (int s = 0; s < steps_input<E, P>(); ++s) c = E::mma(A[s], kB[s], c);
+  return c;
+}
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1, so
+// every register-array index inside the body is a constant.
+template <class F, int... Is>
+__device__ inline void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ inline void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+__device__ constexpr int hess_m(int h, int P) {
+  int c = 0;
+  for (int m = 0; m < P; ++m)
+    for (int n = m; n < P; ++n) {
+      if (c == h) return m;
+      ++c;
+    }
+  return 0;
+}
+__device__ constexpr int hess_n(int h, int P) {
+  int c = 0;
+  for (int m = 0; m < P; ++m)
+    for (int n = m; n < P; ++n) {
+      if (c == h) return n;
+      ++c;
+    }
+  return 0;
+}
+
+template <class E> __device__ inline typename E::acc zero_acc() { return typename E::acc{0, 0, 0, 0}; }
+
+// Sum a per-lane partial over the four lane groups (rows) of the wave.
+__device__ inline double group_sum(double x) {
+  x += __shfl_xor(x, 16);
+  x += __shfl_xor(x, 32);
+  return x;
+}
+
+
+// Sum four per-lane partials p0..p3 (one per column) over the four lane
+// groups of a wave.  On return lane group g holds the full sum of column g
+// for its point (three exchanges instead of eight).
+__device__ inline double reduce4(double p0, double p1, double p2, double p3, int g) {
+  const bool lo = (g & 2) == 0;
+  const double r0 = __shfl_xor(lo ? p2 : p0, 32);
+  const double r1 = __shfl_xor(lo ? p3 : p1, 32);
+  const double k0 = (lo ? p0 : p2) + r0;
+  const double k1 = (lo ? p1 : p3) + r1;
+  const bool even = (g & 1) == 0;
+  const double r = __shfl_xor(even ? k1 : k0, 16);
+  return (even ? k0 : k1) + r;
+}
+
+// Sum over the 16 lanes that share a lane group (the 16 points of a tile).
+__device__ inline double sum16(double x) {
+  x += __shfl_xor(x, 1);
+  x += __shfl_xor(x, 2);
+  x += __shfl_xor(x, 4);
+  x += __shfl_xor(x, 8);
+  return x;
+}
+
+}  // namespace pa

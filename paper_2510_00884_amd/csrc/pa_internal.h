@@ -18,6 +18,7 @@ namespace pa {
 //   x_*:   FP64 matrix-core fragments, y_*: FP32 fragments, z_*: BF16 fragments
 //          W1 [MB][S1][64], A [L][MB][SH][64], B [L][MB][S1][64]
 //          (bf16: [..][64][8] with SHB/1 K steps)
+//          AT (reverse products): lane (i, g) of step s holds A_k[4s + g][16w + i]
 //   k0, nout: scratch used to evaluate the network at K = 0 (normalisation)
 struct PrepLayout {
   int32_t H, L, P, MB, S1, SH, SHB, NOUT;
@@ -27,6 +28,7 @@ struct PrepLayout {
   int64_t x_W1, x_A, x_B;
   int64_t y_W1, y_A, y_B;
   int64_t z_W1, z_A, z_B;
+  int64_t x_AT, y_AT;   // transposed hidden weights for reverse products [L][MB][SH][64]
   int64_t k0, nout;
   int64_t total;
 };
@@ -47,6 +49,8 @@ int launch_invariants(int nsv, int64_t n, const double* F, const ModelConst& mc,
                       double* K, double* dKdF, int32_t* n_bad, hipStream_t s);
 int launch_features(int nsv, int64_t n, const double* F, const ModelConst& mc, double* K,
                     int32_t* n_bad, hipStream_t s);
+int launch_material_cc(int nsv, int64_t n, const double* F, const double* Nout, const ModelConst& mc,
+                       double* SC, hipStream_t s);
 int launch_chain(int nsv, int64_t n, const double* F, const double* Nout, const double* N0,
                  const ModelConst& mc, double* psi, double* P, double* A, int32_t* n_bad, hipStream_t s);
 
@@ -55,17 +59,23 @@ bool mlp_supported(int H, int L, int P);
 int launch_prepare(const PrepLayout& lay, const ThetaLayout& tl, const double* theta,
                    unsigned char* prep, int normalize, int npair, hipStream_t s);
 int launch_mlp(const PrepLayout& lay, int prec, int algo, const unsigned char* prep, int64_t n,
-               const double* K, double* out, hipStream_t s);
+               const double* K, double* out, int hess, hipStream_t s);
+
+// parameter adjoint (adjoint.hip)
+int64_t param_backward_ws(int H, int L, int P, int prec, int64_t n);
+int launch_param_backward(const PrepLayout& lay, const ThetaLayout& tl, int nsv, int prec,
+                          const unsigned char* prep, const ModelConst& mc, int64_t n, const double* F,
+                          const double* P_bar, double* theta_bar, unsigned char* ws, hipStream_t s);
 
 // elements and assembly (fe.hip)
 int launch_geometry(int nen, int64_t n_el, int64_t n_nodes, const double* X, const int32_t* conn,
                     double* dNdX, double* w, int32_t* n_bad, hipStream_t s);
 int launch_gather_F(int nen, int nq, int64_t n_el, const int32_t* conn, const double* dNdX,
                     const double* u, double* F, hipStream_t s);
-int launch_chain_integrate(int nen, int nsv, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
-                           const double* dNdX, const double* w, const double* F, const double* Nout,
-                           const ModelConst& mc, double* r_e, double* K_e, const int64_t* row_ptr,
-                           const int32_t* e2csr, double* r, double* vals, bool scatter, hipStream_t s);
+int launch_chain_integrate(int nen, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
+                           const double* dNdX, const double* w, const double* F, const double* SC,
+                           double* r_e, double* K_e, const int64_t* row_ptr, const int32_t* e2csr, double* r,
+                           double* vals, bool scatter, hipStream_t s);
 int launch_csr_map(int nen, int64_t n_el, const int32_t* conn, const int64_t* row_ptr,
                    const int32_t* col, int32_t* e2csr, hipStream_t s);
 int launch_assemble(int nen, int64_t e_begin, int64_t e_count, const int32_t* perm, int64_t n_el,

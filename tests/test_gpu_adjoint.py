@@ -1,0 +1,99 @@
+"""GPU parity of the parameter adjoint (pa_param_backward) and of the
+torch.autograd.Function built on it.
+
+theta_bar = sum_q (dP_q/dtheta)^T P_bar_q is compared with the oracle's
+vector-Jacobian product (PyTorch reverse mode on the CPU, FP64), with
+central finite differences of the GPU's FP64 forward (h = 1e-6), and with
+the oracle's calibration-loss gradient.  Tolerances (normwise): FP64 1e-10,
+FP32 1e-4."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import calib, ncm
+from paper_2510_00884_amd import synth
+from gpu_util import close, need_gpu, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_vjp(theta, F, Pbar, Av, p, h, L, has_bias=True):
+    K, g = calib.feature_grads(F, Av)
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    P = calib.stress_from_theta(th, torch.tensor(K), torch.tensor(g), p, h, L, has_bias)
+    out, = torch.autograd.grad(P, th, torch.tensor(Pbar))
+    return out.numpy(), P.detach().numpy()
+
+
+@pytest.mark.parametrize("n_sv,h,L,bias", [(2, 16, 2, True), (2, 64, 3, True), (1, 32, 3, True),
+                                           (0, 32, 2, False), (2, 32, 2, True)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_param_backward_vs_oracle(n_sv, h, L, bias, prec, tol):
+    api = need_gpu()
+    say("param_backward", n_sv, h, L, bias, prec)
+    p = synth.num_inputs(n_sv)
+    Av = synth.structural_vectors(n_sv)
+    theta = synth.micnn_params(p, h, L, seed=1, has_bias=bias)
+    n = 700  # 43 full tiles of 16 and a ragged tail
+    F = synth.sample_F(n, seed=3)
+    Pbar = synth.rng(7).normal(size=(n, 3, 3))
+    ref, Pref = oracle_vjp(theta, F, Pbar, Av, p, h, L, bias)
+    gm = api.Model(theta, n_sv, h, L, A=Av, normalize=False, has_bias=bias)
+    tb = api.param_backward(gm, torch.tensor(F, device="cuda"), torch.tensor(Pbar, device="cuda"), prec=prec)
+    e = close(tb.cpu().numpy(), ref, tol, "theta_bar")
+    say("  err", e)
+    # the stress the forward returns for this model
+    out = api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec="fp64", A=False, psi=False)
+    close(out["P"].cpu().numpy().T.reshape(n, 3, 3), Pref, 1e-12, "P")
+
+
+def test_param_backward_deterministic_and_empty():
+    api = need_gpu()
+    p = synth.num_inputs(2)
+    theta = synth.micnn_params(p, 32, 2, seed=1)
+    gm = api.Model(theta, 2, 32, 2, A=synth.structural_vectors(2))
+    F = torch.tensor(synth.sample_F(5000, seed=1), device="cuda")
+    Pb = torch.tensor(synth.rng(2).normal(size=(5000, 3, 3)), device="cuda")
+    a = api.param_backward(gm, F, Pb, prec="fp64")
+    b = api.param_backward(gm, F, Pb, prec="fp64")
+    assert torch.equal(a, b)
+    z = api.param_backward(gm, F[:0], Pb[:0], prec="fp64")
+    assert torch.count_nonzero(z).item() == 0
+
+
+def test_autograd_function_and_finite_differences():
+    api = need_gpu()
+    say("autograd + FD")
+    n_sv, h, L = 2, 16, 3
+    p = synth.num_inputs(n_sv)
+    Av = synth.structural_vectors(n_sv)
+    theta = synth.micnn_params(p, h, L, seed=1)
+    theta_ref = synth.micnn_params(p, h, L, seed=4)
+    n = 512
+    F = synth.sample_F(n, seed=3)
+    Pref = ncm.stress_stiffness(F, ncm.model_from_theta(theta_ref, p, h, L, Av))["P"]
+    Pt = Pref + 0.01 * np.sqrt(np.mean(Pref ** 2)) * synth.rng(5).normal(size=Pref.shape)
+    Lo, go = calib.loss_and_grad(theta, F, Pt, Av, p, h, L)
+    gm = api.Model(theta, n_sv, h, L, A=Av)
+    th = torch.tensor(theta, device="cuda", requires_grad=True)
+    Ft = torch.tensor(F, device="cuda")
+    Ptt = torch.tensor(Pt, device="cuda")
+    P = api.stress(th, Ft, gm, prec="fp64")
+    loss = ((P - Ptt) ** 2).sum() / n
+    loss.backward()
+    assert abs(loss.item() - Lo) < 1e-12 * abs(Lo)
+    close(th.grad.cpu().numpy(), go, 1e-10, "dL/dtheta")
+
+    def gpu_loss(tv):
+        m = api.Model(tv, n_sv, h, L, A=Av)
+        Pg = api.energy_stress_tangent(m, Ft, prec="fp64", psi=False, A=False)["P"].t().reshape(n, 3, 3)
+        return (((Pg - Ptt) ** 2).sum() / n).item()
+
+    hstep = 1e-6
+    idx = synth.rng(9).choice(theta.size, 12, replace=False)
+    g = th.grad.cpu().numpy()
+    for i in idx:
+        e = np.zeros_like(theta)
+        e[i] = hstep
+        fd = (gpu_loss(theta + e) - gpu_loss(theta - e)) / (2 * hstep)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, np.abs(g).max()), (i, fd, g[i])
