@@ -38,6 +38,19 @@ def mlp_flops_per_point(h, L, p):
     return 2 * h * h * c * (L - 1) + 2 * h * c + 2 * h * p * L + 4 * h * P2 * (L - 1) + h * P2
 
 
+def mlp_adjoint_flops_per_point(h, L, p):
+    """Adjoint-form Hessian: value forward 2hp + (L-1)(2h^2 + 2hp), value
+    adjoint (L-1) 2h^2, Jacobian forward (L-1) 2h^2 p, Gram sums 3 h P2 L,
+    gradient 2hp."""
+    P2 = p * (p + 1) // 2
+    return 2 * h * p + (L - 1) * (2 * h * h + 2 * h * p) + (L - 1) * 2 * h * h + (L - 1) * 2 * h * h * p \
+        + 3 * h * P2 * L + 2 * h * p
+
+
+def mlp_flops(kernel, h, L, p):
+    return (mlp_adjoint_flops_per_point if kernel == "mlp_adjoint" else mlp_flops_per_point)(h, L, p)
+
+
 def kernel_bytes(name, nen, nq, p):
     """Algorithmic HBM bytes per element for the bandwidth-bound kernels:
     every input read once and every output written once (read-modify-write
@@ -87,7 +100,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=64, help="cubes per side of the hex8 mesh")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16", "bf16_corr"])
-    ap.add_argument("--algo", default="forward", choices=["forward", "adjoint"])
+    ap.add_argument("--algo", default="adjoint", choices=["forward", "adjoint"],
+                    help="network Hessian formation (BF16 variants always use forward)")
     ap.add_argument("--variants", default="fp32,bf16,bf16_corr",
                     help="other precisions timed after the headline run ('' for none)")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="elements in the oracle CPU sample (0: skip)")
@@ -169,11 +183,11 @@ def main():
     if dom:
         per_launch_s = kern[dom]["ms_per_launch"] / 1e3
         if dom.startswith("mlp"):
-            fl = mlp_flops_per_point(h, Lh, p) * n_qp
+            fl = mlp_flops(dom, h, Lh, p) * n_qp
             ach = fl / per_launch_s
             roof = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[args.prec] / 1e12, "unit": "TFLOP/s",
                     "frac": ach / PEAK[args.prec], "traffic": None, "kernel": dom,
-                    "algorithmic_per_launch": f"{mlp_flops_per_point(h, Lh, p)} FLOP/point x {n_qp} points"}
+                    "algorithmic_per_launch": f"{mlp_flops(dom, h, Lh, p)} FLOP/point x {n_qp} points"}
         else:
             launches_per_step = kern[dom]["launches"] / args.steps
             b = kernel_bytes(dom, mesh.nen, mesh.nq, p) * mesh.n_el / launches_per_step
@@ -184,14 +198,16 @@ def main():
 
     variants = {}
     for vp in [x for x in args.variants.split(",") if x and x != args.prec]:
+        # the adjoint-form Hessian has FP64 and FP32 kernels only
+        model.algorithm = args.algo if vp in ("fp64", "fp32") else "forward"
         vms, vk = run(vp, max(args.steps // 2, 2), 1, True)
         err_r = (bufs["r"] - r_ref).norm().item() / r_ref.norm().item()
         err_K = (bufs["vals"] - v_ref).norm().item() / v_ref.norm().item()
         mk = next((k for k in vk if k.startswith("mlp")), None)
-        variants[vp] = {"value": n_qp / (vms / 1e3), "ms_per_step": vms,
+        variants[vp] = {"value": n_qp / (vms / 1e3), "ms_per_step": vms, "algorithm": model.algorithm_name,
                         "rel_err_vs_fp64_r": err_r, "rel_err_vs_fp64_K": err_K,
                         "mlp_ms": vk[mk]["ms_per_launch"] if mk else None,
-                        "mlp_tflops": (mlp_flops_per_point(h, Lh, p) * n_qp / (vk[mk]["ms_per_launch"] / 1e3) / 1e12) if mk else None}
+                        "mlp_tflops": (mlp_flops(mk, h, Lh, p) * n_qp / (vk[mk]["ms_per_launch"] / 1e3) / 1e12) if mk else None}
         print(f"[bench] {vp}: {vms:.3f} ms/step, err r {err_r:.2e} K {err_K:.2e}", file=sys.stderr, flush=True)
 
     cpu = None

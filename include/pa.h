@@ -63,8 +63,10 @@ typedef enum {
 typedef enum {
   PA_ALGO_FORWARD = 0, /* one-pass forward mode of App. B.2 Alg. 4: value,
                           gradient and Hessian columns carried layer by layer */
-  PA_ALGO_ADJOINT = 1  /* value and Jacobian forward, value adjoint backward,
-                          Hessian as sum_k J_k^T diag(lambda_k F''(y_k)) J_k   */
+  PA_ALGO_ADJOINT = 1  /* value forward, value adjoint backward, then the
+                          Jacobian forward accumulating the Hessian as
+                          sum_k J_k^T diag(lambda_k F''(y_k)) J_k; FP64 and
+                          FP32 only (BF16 precisions: PA_ERR_UNSUPPORTED)    */
 } pa_algorithm;
 
 typedef enum { PA_ACT_SOFTPLUS = 0 } pa_activation;

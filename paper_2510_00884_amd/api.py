@@ -87,6 +87,10 @@ class Model:
     def algorithm(self):
         return self.desc.algorithm
 
+    @property
+    def algorithm_name(self):
+        return {v: k for k, v in L.ALGORITHMS.items()}[self.desc.algorithm]
+
     @algorithm.setter
     def algorithm(self, a):
         self.desc.algorithm = L.ALGORITHMS[a] if isinstance(a, str) else int(a)

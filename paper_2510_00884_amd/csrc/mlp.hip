@@ -557,6 +557,272 @@ k_mlp_fwd(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   }
 }
 
+// ---------------------------------------------------------------- adjoint-form Hessian
+// Same outputs as k_mlp_fwd.  The Hessian of N = a.z_L + b.K in the inputs is
+//   d2N/dK dK = sum_k J_k^T diag(lambda_k (.) F''(y_k)) J_k,
+// J_k = dy_k/dK (h x p), lambda_k = dN/dz_k, lambda_L = a,
+// lambda_{k-1} = A_k^T (lambda_k (.) F'(y_k)),
+// because every second derivative of N enters through the curvature of an
+// activation (the layers are affine).  Passes per tile:
+//   1. value forward (all layers), 2. reverse sweep for lambda_k (one column,
+//   products with A_k^T), 3. Jacobian forward (p columns) accumulating the
+//   Gram sums layer by layer, so only one layer of J is live at a time.
+// Points on the N dimension, neurons split across waves as in k_mlp_fwd.
+template <int H, int L, int P, int PR>
+__global__ void __launch_bounds__(64 * (H / 16))
+k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
+          const double* __restrict__ Kin, double* __restrict__ out, int hess) {
+  using E = typename std::conditional<PR == PREC_F64, EngF64, EngF32>::type;
+  using T = typename E::T;
+  using acc_t = typename E::acc;
+  constexpr int MB = H / 16, NW = MB, P2 = P * (P + 1) / 2, NOUT = 1 + P + P2;
+  constexpr int SH = H / 4, S1 = (P + 3) / 4;
+  constexpr int CH = (L >= 3) ? 3 : 1;  // gradient columns per LDS exchange chunk
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
+  const int64_t base = (int64_t)blockIdx.x * 16;
+  const int64_t qp = base + q;
+  const bool valid = qp < n;
+
+  __shared__ T W1s[P][H];
+  __shared__ double outp[NW][NOUT][16];
+  __shared__ T xbuf[CH][H][16];
+
+  const bool dbl = std::is_same<T, double>::value;
+  const T* t_W1t = (const T*)(prep + (dbl ? lay.d_W1t : lay.f_W1t));
+  const T* t_a = (const T*)(prep + (dbl ? lay.d_a : lay.f_a));
+  const T* t_c = (const T*)(prep + (dbl ? lay.d_c : lay.f_c));
+  const T* t_Bt = (const T*)(prep + (dbl ? lay.d_Bt : lay.f_Bt));
+  const double* d_b = (const double*)(prep + lay.d_b);
+  const typename E::frag* fW1 = frag_ptr<E>(prep, lay, 0);
+  const typename E::frag* fA = frag_ptr<E>(prep, lay, 1);
+  const typename E::frag* fB = frag_ptr<E>(prep, lay, 2);
+  const typename E::frag* fAT = (const typename E::frag*)(prep + (dbl ? lay.x_AT : lay.y_AT));
+
+  for (int i = tid; i < P * H; i += 64 * NW) W1s[i / H][i % H] = t_W1t[i];
+  typename E::frag kB[S1];
+#pragma unroll
+  for (int s = 0; s < S1; ++s) {
+    const int m = 4 * s + g;
+    kB[s] = (valid && m < P) ? (T)Kin[(int64_t)m * n + qp] : (T)0;
+  }
+  // layer 1, all rows
+  T s1[MB][4], t1[MB][4], z1[MB][4];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    typename E::frag a1[S1];
+#pragma unroll
+    for (int s = 0; s < S1; ++s) a1[s] = fW1[(mb * S1 + s) * 64 + lane];
+    acc_t acc = mma_in<E, P>(a1, kB, zero_acc<E>());
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      T f, f1, f2;
+      softplus3((T)(acc[v] + t_c[16 * mb + E::row(g, v)]), f, f1, f2);
+      z1[mb][v] = f; s1[mb][v] = f1; t1[mb][v] = f2;
+    }
+  }
+  typename E::frag AV[L - 1][SH], BV[L - 1][S1];
+#pragma unroll
+  for (int k = 2; k <= L; ++k) {
+#pragma unroll
+    for (int s = 0; s < SH; ++s) AV[k - 2][s] = fA[(((k - 1) * MB + w) * SH + s) * 64 + lane];
+#pragma unroll
+    for (int s = 0; s < S1; ++s) BV[k - 2][s] = fB[(((k - 1) * MB + w) * S1 + s) * 64 + lane];
+  }
+  T a_own[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) a_own[v] = t_a[16 * w + E::row(g, v)];
+  __syncthreads();  // W1s
+
+  // ---- 1. value forward (own rows of layers 2..L)
+  T sk[L - 1][4], tk[L - 1][4];
+  {
+    T src[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) src[mb][v] = z1[mb][v];
+    static_for<L - 1>([&](auto KI) {
+      constexpr int k = decltype(KI)::value + 2;
+      if constexpr (k >= 3) {
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) src[mb][v] = xbuf[0][16 * mb + E::row(g, v)][q];
+        __syncthreads();
+      }
+      acc_t acc = mma_in<E, P>(BV[k - 2], kB, mma_src<E, MB>(AV[k - 2], src, zero_acc<E>()));
+      T o[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        T f, f1, f2;
+        softplus3((T)(acc[v] + t_c[(k - 1) * H + 16 * w + E::row(g, v)]), f, f1, f2);
+        sk[k - 2][v] = f1; tk[k - 2][v] = f2; o[v] = f;
+      }
+      if constexpr (k < L) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xbuf[0][16 * w + E::row(g, v)][q] = o[v];
+      } else {
+        double pl = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pl += (double)(a_own[v] * o[v]);
+        pl = group_sum(pl);
+        if (g == 0) outp[w][0][q] = pl;
+      }
+    });
+  }
+
+  // ---- 2. reverse sweep: gamma_k = lambda_k (.) F''(y_k), own rows
+  T gam[L][4];
+  if (hess) {
+    T lam[4], mu[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      lam[v] = a_own[v];
+      gam[L - 1][v] = lam[v] * tk[L - 2][v];
+      mu[v] = lam[v] * sk[L - 2][v];
+    }
+    static_for<L - 1>([&](auto KI) {
+      constexpr int k = L - decltype(KI)::value;  // L .. 2: lambda_{k-1} = A_k^T mu_k
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xbuf[0][16 * w + E::row(g, v)][q] = mu[v];
+      __syncthreads();
+      const typename E::frag* at = fAT + (((k - 1) * MB + w) * SH) * 64 + lane;
+      acc_t acc = zero_acc<E>();
+#pragma unroll
+      for (int s = 0; s < SH; ++s) acc = E::mma(at[s * 64], (typename E::frag)xbuf[0][4 * s + g][q], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T l = (T)acc[v];
+        if constexpr (k - 1 >= 2) {
+          gam[k - 2][v] = l * tk[k - 3][v];
+          mu[v] = l * sk[k - 3][v];
+        } else {
+          gam[0][v] = l * t1[w][v];
+        }
+      }
+    });
+    __syncthreads();  // xbuf free
+  }
+
+  // ---- 3. Jacobian forward with the Gram sums
+  T Hp[P2];
+#pragma unroll
+  for (int h = 0; h < P2; ++h) Hp[h] = (T)0;
+  if (hess) {  // layer 1: J_1 = W1 (own rows of block w)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * w + E::row(g, v);
+      T wr[P];
+#pragma unroll
+      for (int m = 0; m < P; ++m) wr[m] = W1s[m][r];
+      static_for<P2>([&](auto HI) {
+        constexpr int h = decltype(HI)::value;
+        constexpr int m = hess_m(h, P), nn = hess_n(h, P);
+        Hp[h] += gam[0][v] * wr[m] * wr[nn];
+      });
+    }
+  }
+  T J[P][4];  // dy_k/dK_m, own rows of the current layer
+  static_for<L - 1>([&](auto KI) {
+    constexpr int k = decltype(KI)::value + 2;
+    if constexpr (k == 2) {
+      static_for<P>([&](auto MI) {
+        constexpr int m = decltype(MI)::value;
+        T src[MB][4];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) src[mb][v] = s1[mb][v] * W1s[m][16 * mb + E::row(g, v)];
+        acc_t acc = mma_src<E, MB>(AV[0], src, zero_acc<E>());
+#pragma unroll
+        for (int v = 0; v < 4; ++v) J[m][v] = (T)acc[v] + t_Bt[((int64_t)1 * P + m) * H + 16 * w + E::row(g, v)];
+      });
+    } else {
+      // exchange dz_{k-1}/dK_m = F'(y_{k-1}) J_{k-1} in chunks of CH columns
+      static_for<(P + CH - 1) / CH>([&](auto CI) {
+        constexpr int c0 = decltype(CI)::value * CH;
+        __syncthreads();
+        static_for<CH>([&](auto JI) {
+          constexpr int m = c0 + decltype(JI)::value;
+          if constexpr (m < P) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xbuf[m - c0][16 * w + E::row(g, v)][q] = sk[k - 3][v] * J[m][v];
+          }
+        });
+        __syncthreads();
+        static_for<CH>([&](auto JI) {
+          constexpr int m = c0 + decltype(JI)::value;
+          if constexpr (m < P) {
+            T src[MB][4];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) src[mb][v] = xbuf[m - c0][16 * mb + E::row(g, v)][q];
+            acc_t acc = mma_src<E, MB>(AV[k - 2], src, zero_acc<E>());
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              J[m][v] = (T)acc[v] + t_Bt[((int64_t)(k - 1) * P + m) * H + 16 * w + E::row(g, v)];
+          }
+        });
+      });
+    }
+    if (hess) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        static_for<P2>([&](auto HI) {
+          constexpr int h = decltype(HI)::value;
+          constexpr int m = hess_m(h, P), nn = hess_n(h, P);
+          Hp[h] += gam[k - 1][v] * J[m][v] * J[nn][v];
+        });
+    }
+  });
+  // gradient outputs: dN/dK_m = sum_j a_j F'(y_L,j) J_L[j, m] (+ b_m below)
+  static_for<(P + 3) / 4>([&](auto BI) {
+    constexpr int c0 = decltype(BI)::value * 4;
+    double pp[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double x = 0.0;
+      if (c0 + j < P) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x += (double)(a_own[v] * sk[L - 2][v] * J[c0 + j < P ? c0 + j : 0][v]);
+      }
+      pp[j] = x;
+    }
+    const double r = reduce4(pp[0], pp[1], pp[2], pp[3], g);
+    if (c0 + g < P) outp[w][1 + c0 + g][q] = r;
+  });
+  if (hess) {
+    static_for<(P2 + 3) / 4>([&](auto BI) {
+      constexpr int c0 = decltype(BI)::value * 4;
+      double pp[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pp[j] = (c0 + j < P2) ? (double)Hp[c0 + j < P2 ? c0 + j : 0] : 0.0;
+      const double r = reduce4(pp[0], pp[1], pp[2], pp[3], g);
+      if (c0 + g < P2) outp[w][1 + P + c0 + g][q] = r;
+    });
+  }
+
+  __syncthreads();
+  const int nout_written = hess ? NOUT : 1 + P;
+  for (int i = tid; i < nout_written * 16; i += 64 * NW) {
+    const int c = i / 16, qq = i % 16;
+    const int64_t pt = base + qq;
+    if (pt >= n) continue;
+    double v = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) v += outp[ww][c][qq];
+    if (c == 0) {
+      for (int m = 0; m < P; ++m) v += d_b[m] * Kin[(int64_t)m * n + pt];
+    } else if (c <= P) {
+      v += d_b[c - 1];
+    }
+    out[(int64_t)c * n + pt] = v;
+  }
+}
+
 // ---------------------------------------------------------------- dispatch
 template <int H, int L, int P>
 static int launch_mlp_t(const PrepLayout& lay, int prec, const unsigned char* prep, int64_t n,
@@ -585,9 +851,29 @@ bool mlp_supported(int H, int L, int P) {
   return false;
 }
 
+template <int H, int L, int P>
+static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char* prep, int64_t n,
+                            const double* K, double* out, int hess, hipStream_t s) {
+  const unsigned grid = (unsigned)((n + 15) / 16);
+  const unsigned block = 64 * (H / 16);
+  switch (prec) {
+    case PREC_F64: k_mlp_adj<H, L, P, PREC_F64><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
+    case PREC_F32: k_mlp_adj<H, L, P, PREC_F32><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
+    default: return -2;
+  }
+  return 0;
+}
+
 int launch_mlp(const PrepLayout& lay, int prec, int algo, const unsigned char* prep, int64_t n,
                const double* K, double* out, int hess, hipStream_t s) {
   if (n == 0) return 0;
+  if (algo == 1) {
+#define PA_DISPATCH_ADJ(h, l, p) \
+    if (lay.H == h && lay.L == l && lay.P == p) return launch_mlp_adj_t<h, l, p>(lay, prec, prep, n, K, out, hess, s);
+    PA_MLP_CONFIGS(PA_DISPATCH_ADJ)
+#undef PA_DISPATCH_ADJ
+    return -2;
+  }
   if (algo != 0) return -2;
 #define PA_DISPATCH(h, l, p) \
   if (lay.H == h && lay.L == l && lay.P == p) return launch_mlp_t<h, l, p>(lay, prec, prep, n, K, out, hess, s);

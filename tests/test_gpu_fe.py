@@ -100,3 +100,20 @@ def test_homogeneous_and_rigid_motion():
     t = torch.tensor(np.tile([0.3, -1.1, 0.7], 8), device="cuda")
     assert (K_e @ t).abs().max().item() < 1e-11 * K_e.abs().max().item()
     assert (K_e - K_e.transpose(1, 2)).abs().max().item() < 1e-12 * K_e.abs().max().item()
+
+
+@pytest.mark.parametrize("kind,n,n_sv,h,L", [("hex8", 5, 2, 32, 2), ("tet10", 2, 2, 64, 3)])
+def test_tangent_build_adjoint_hessian(kind, n, n_sv, h, L):
+    """The fused tangent build with the adjoint-form network Hessian matches
+    the oracle's assembled residual and tangent."""
+    api = need_gpu()
+    say("tangent_build adjoint", kind, n, n_sv, h, L)
+    X, conn, gm, om, mesh, u = setup(api, kind, n, n_sv, h, L)
+    gm.algorithm = "adjoint"
+    cperm = conn[mesh.perm]
+    dNdX, w, _ = fe.geometry(X, cperm)
+    r_ref, K_ref, _ = fe.element_residual_stiffness(u, cperm, dNdX, w, om)
+    rg, Kg = fe.assemble(cperm, r_ref, K_ref, X.shape[0])
+    rf, vf = api.tangent_build(gm, mesh, torch.tensor(u, device="cuda"), prec="fp64")
+    close(rf.cpu().numpy(), rg, 1e-12, "r")
+    close(vf.cpu().numpy(), Kg.data, 1e-12, "vals")

@@ -112,3 +112,49 @@ def test_precision_ladder(prec, tol_psi, tol_P, tol_A, n_sv, h, L):
     e = (rel(psi, ref["psi"]), rel(P, ref["P"]), rel(A, ref["A"]))
     say("  errors psi/P/A", e)
     assert e[0] < tol_psi and e[1] < tol_P and e[2] < tol_A
+
+
+@pytest.mark.parametrize("n_sv,h,L,normalize", CASES)
+def test_adjoint_hessian_fp64(n_sv, h, L, normalize):
+    """The adjoint-form Hessian (sum over layers of J^T diag(lambda F'') J)
+    against the oracle's forward-mode tables, and against the library's own
+    forward algorithm (same numbers up to rounding order)."""
+    api = need_gpu()
+    say("material adjoint fp64", n_sv, h, L, normalize)
+    gm, om = build(api, n_sv, h, L, normalize, algorithm="adjoint")
+    n = 1000
+    F = synth.sample_F(n, seed=0)
+    Ft = torch.tensor(F, device="cuda")
+    out = api.energy_stress_tangent(gm, Ft, prec="fp64")
+    psi, P, A = unpack(out, n)
+    ref = ncm.stress_stiffness(F, om)
+    close(psi, ref["psi"], 1e-12, "psi")
+    close(P, ref["P"], 1e-12, "P")
+    close(A, ref["A"], 1e-12, "A")
+    gm.algorithm = "forward"
+    fw = api.energy_stress_tangent(gm, Ft, prec="fp64")
+    close(out["A"].cpu().numpy(), fw["A"].cpu().numpy(), 1e-13, "A adjoint vs forward")
+
+
+@pytest.mark.parametrize("n_sv,h,L", [(2, 32, 2), (2, 64, 3), (0, 16, 2)])
+def test_adjoint_hessian_fp32(n_sv, h, L):
+    api = need_gpu()
+    say("material adjoint fp32", n_sv, h, L)
+    gm, om = build(api, n_sv, h, L, True, algorithm="adjoint")
+    n = 2000
+    F = synth.sample_F(n, seed=5)
+    out = api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec="fp32")
+    psi, P, A = unpack(out, n)
+    ref = ncm.stress_stiffness(F, om)
+    e = (rel(psi, ref["psi"]), rel(P, ref["P"]), rel(A, ref["A"]))
+    say("  errors psi/P/A", e)
+    assert max(e) < 1e-5
+
+
+def test_adjoint_bf16_unsupported():
+    api = need_gpu()
+    gm, _ = build(api, 2, 32, 2, True, algorithm="adjoint")
+    F = torch.tensor(synth.sample_F(32, seed=5), device="cuda")
+    from paper_2510_00884_amd._lib import PaError
+    with pytest.raises(PaError):
+        api.energy_stress_tangent(gm, F, prec="bf16")
