@@ -10,7 +10,7 @@ u_i = 0.05 sin(pi X_i) + 0.05 sin(pi X_{i+1}) + 0.02 h U[-1, 1] (seed 0).
 
 A step is the whole path u -> F -> features -> network (value, gradient,
 Hessian) -> chain rule (P, dP/dF) -> element residual and stiffness ->
-coloured CSR assembly of r and K.  Inputs are resident on the GPU before the
+CSR assembly of r and K.  Inputs are resident on the GPU before the
 timed region.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -51,6 +51,16 @@ def mlp_flops(kernel, h, L, p):
     return (mlp_adjoint_flops_per_point if kernel == "mlp_adjoint" else mlp_flops_per_point)(h, L, p)
 
 
+def kernel_bytes_total(name, mesh, p):
+    """Algorithmic HBM bytes of one step for a bandwidth-bound kernel."""
+    if name == "gather_assemble":
+        nd = 3 * mesh.nen
+        return mesh.n_el * (8 * nd * nd + 8 * nd + 4 * mesh.nen * mesh.nen + 4 * mesh.nen) \
+            + 8 * mesh.nnz + 8 * 3 * mesh.n_nodes + 8 * (3 * mesh.n_nodes + 1) + 8 * (mesh.n_nodes + 1)
+    b = kernel_bytes(name, mesh.nen, mesh.nq, p)
+    return None if b is None else b * mesh.n_el
+
+
 def kernel_bytes(name, nen, nq, p):
     """Algorithmic HBM bytes per element for the bandwidth-bound kernels:
     every input read once and every output written once (read-modify-write
@@ -63,7 +73,7 @@ def kernel_bytes(name, nen, nq, p):
     if name == "material_cc":
         return nq * (72 + 8 * (nout - 1) + 8 * 27)              # F, network derivatives in; S~, CC~ out
     inputs = nq * (72 + 8 * 27 + 8) + nq * nen * 3 * 8           # F, S~ and CC~, w, dN/dX
-    if name == "integrate":
+    if name in ("integrate", "integrate_elmajor"):
         return inputs + 8 * nd * nd + 8 * nd                     # K_e, r_e written
     if name == "integrate_scatter":
         return inputs + 16 * nd * nd + 16 * nd + 4 * nen * nen   # CSR and r read-modify-write, CSR map
@@ -105,8 +115,9 @@ def main():
     ap.add_argument("--variants", default="fp32,bf16,bf16_corr",
                     help="other precisions timed after the headline run ('' for none)")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="elements in the oracle CPU sample (0: skip)")
-    ap.add_argument("--unfused", action="store_true",
-                    help="element tables + separate assembly instead of the fused per-colour build")
+    ap.add_argument("--assembly", default="gather", choices=["gather", "coloured", "tables"],
+                    help="gather: element-major tables + one pass per node (default); coloured: element rows "
+                         "scattered into CSR colour by colour; tables: element tables + coloured assembly")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -133,9 +144,11 @@ def main():
     model = api.Model(theta, n_sv, h, Lh, A=Av, normalize=True, algorithm=args.algo)
     mesh = api.FEMesh(X, conn, colour=par)
     ut = torch.tensor(u, device="cuda").reshape(-1).contiguous()
-    ws = torch.empty(mesh.workspace_bytes(model), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(mesh.workspace_bytes(model, "gather" if args.assembly == "gather" else "coloured"),
+                     dtype=torch.uint8, device="cuda")
     bufs = {}
-    api.tangent_build(model, mesh, ut, prec=args.prec, workspace=ws, bufs=bufs, fused=not args.unfused)
+    api.tangent_build(model, mesh, ut, prec=args.prec, workspace=ws, bufs=bufs, fused=args.assembly != "tables",
+                          assembly="gather" if args.assembly == "gather" else "coloured")
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     print(f"[bench] setup {t_setup:.1f} s: {mesh.n_el} elements, {mesh.n_el * mesh.nq} points, "
@@ -145,7 +158,8 @@ def main():
 
     def run(prec, steps, warmup, profile):
         for _ in range(warmup):
-            api.tangent_build(model, mesh, ut, prec=prec, workspace=ws, bufs=bufs, fused=not args.unfused)
+            api.tangent_build(model, mesh, ut, prec=prec, workspace=ws, bufs=bufs, fused=args.assembly != "tables",
+                          assembly="gather" if args.assembly == "gather" else "coloured")
         torch.cuda.synchronize()
         if profile:
             lib.pa_profile_enable(1)
@@ -153,7 +167,8 @@ def main():
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(steps):
-            api.tangent_build(model, mesh, ut, prec=prec, workspace=ws, bufs=bufs, fused=not args.unfused)
+            api.tangent_build(model, mesh, ut, prec=prec, workspace=ws, bufs=bufs, fused=args.assembly != "tables",
+                          assembly="gather" if args.assembly == "gather" else "coloured")
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
@@ -177,6 +192,17 @@ def main():
     v_ref = bufs["vals"].clone()
     print(f"[bench] {args.prec}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # per-kernel achieved rates against the algorithmic work
+    for k, v in kern.items():
+        per_step_ms = v["ms_total"] / args.steps
+        if k.startswith("mlp"):
+            v["tflops"] = mlp_flops(k, h, Lh, p) * n_qp / (per_step_ms / 1e3) / 1e12
+        else:
+            b = kernel_bytes_total(k, mesh, p)
+            if b:
+                v["algorithmic_gb_per_step"] = b / 1e9
+                v["gb_s"] = b / (per_step_ms / 1e3) / 1e9
+
     # dominant kernel and its roofline
     dom = max(kern, key=lambda k: kern[k]["ms_total"]) if kern else None
     roof = None
@@ -190,7 +216,7 @@ def main():
                     "algorithmic_per_launch": f"{mlp_flops(dom, h, Lh, p)} FLOP/point x {n_qp} points"}
         else:
             launches_per_step = kern[dom]["launches"] / args.steps
-            b = kernel_bytes(dom, mesh.nen, mesh.nq, p) * mesh.n_el / launches_per_step
+            b = kernel_bytes_total(dom, mesh, p) / launches_per_step
             per_launch_s = kern[dom]["ms_total"] / kern[dom]["launches"] / 1e3
             ach = b / per_launch_s
             roof = {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
@@ -229,8 +255,10 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "bf16_corr": "bf16+f32"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"hex8 {n}^3 unit cube, orthotropic e1/e2 (9 inputs), MICNN 2x32 softplus, "
-                               "one Newton tangent build: residual + tangent + coloured CSR assembly",
-                   "path": "element tables + assembly" if args.unfused else "fused per-colour build",
+                               "one Newton tangent build: residual + tangent + CSR assembly",
+                   "assembly": {"gather": "element-major tables + node-centric gather",
+                                "coloured": "fused per-colour scatter",
+                                "tables": "element tables + coloured assembly"}[args.assembly],
                    "elements": mesh.n_el, "points": n_qp, "dofs": 3 * mesh.n_nodes, "nnz": mesh.nnz,
                    "colours": mesh.n_colours, "precision": args.prec, "algorithm": args.algo},
         "elements_per_s": mesh.n_el / (ms / 1e3),

@@ -128,6 +128,15 @@ typedef struct {
                                  (elements already numbered colour by colour) */
 } pa_colouring;
 
+/* Node incidence for the gather assembly (pa_node_incidence). */
+typedef struct {
+  int64_t n_nodes;
+  int64_t n_ent;         /* n_el * nen                                        */
+  int32_t max_row;       /* >= the longest CSR row (3 x neighbours of a node)  */
+  const int64_t* ptr;    /* [n_nodes + 1] into ent                            */
+  const int32_t* ent;    /* [n_ent] e * nen + a, ascending e within a node     */
+} pa_incidence;
+
 /* ---------------------------------------------------------------- model */
 int32_t pa_num_inputs(const pa_model_desc* desc);
 int64_t pa_num_params(const pa_model_desc* desc);
@@ -225,6 +234,27 @@ int pa_assemble_csr(const pa_mesh* mesh, const pa_colouring* colouring, const pa
 int pa_tangent_build(const pa_model_desc* desc, const void* prepared, int prec, const pa_mesh* mesh,
                      const pa_colouring* colouring, const pa_csr* csr, const double* u, double* r,
                      double* vals, int32_t* n_bad, void* workspace, size_t ws_bytes, void* stream);
+
+/* HOST setup.  Node incidence: for node i, ent[ptr[i] .. ptr[i+1]) lists
+ * e * nen + a for every element e whose local node a is i, in ascending e.
+ * ptr: host [n_nodes + 1]; ent: host [n_el * nen] or NULL (then only ptr). */
+int pa_node_incidence(int32_t nen, int64_t n_el, int64_t n_nodes, const int32_t* conn_host,
+                      int64_t* ptr, int32_t* ent);
+/* Workspace of pa_tangent_build_gather: pa_element_workspace_bytes plus the
+ * element-major tables r_e [n_el][nd] and K_e [n_el][nd][nd]. */
+size_t pa_gather_workspace_bytes(const pa_model_desc* desc, const pa_mesh* mesh);
+/* One Newton tangent build with node-centric assembly (same result as
+ * pa_tangent_build up to summation order): elements are integrated in one
+ * launch into element-major tables, then one wave per node sums its
+ * elements' rows (incidence order) and writes its three CSR rows and r
+ * entries once.  Every entry of r and vals is overwritten (no clearing
+ * needed); the result is bitwise reproducible and needs no colouring.
+ * Needs csr->row_ptr and csr->e2csr; r or vals may be NULL.  Rows longer
+ * than inc->max_row are left untouched.  workspace:
+ * pa_gather_workspace_bytes(desc, mesh). */
+int pa_tangent_build_gather(const pa_model_desc* desc, const void* prepared, int prec, const pa_mesh* mesh,
+                            const pa_incidence* inc, const pa_csr* csr, const double* u, double* r,
+                            double* vals, int32_t* n_bad, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- adjoint */
 size_t pa_param_backward_workspace(const pa_model_desc* desc, int prec, int64_t n_qp);

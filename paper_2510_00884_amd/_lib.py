@@ -36,6 +36,11 @@ class Csr(C.Structure):
                 ("col", C.c_void_p), ("e2csr", C.c_void_p)]
 
 
+class Incidence(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_ent", C.c_int64), ("max_row", C.c_int32), ("ptr", C.c_void_p),
+                ("ent", C.c_void_p)]
+
+
 class Colouring(C.Structure):
     _fields_ = [("n_colours", C.c_int32), ("colour_ptr", C.c_void_p), ("elem_perm", C.c_void_p)]
 
@@ -64,6 +69,10 @@ SIGNATURES = {
     "pa_element_csr_map": (C.c_int, [PMESH, PCSR, P, P]),
     "pa_assemble_csr": (C.c_int, [PMESH, PCOL, PCSR, P, P, P, P, I32, P]),
     "pa_tangent_build": (C.c_int, [PDESC, P, C.c_int, PMESH, PCOL, PCSR, P, P, P, P, P, SZ, P]),
+    "pa_node_incidence": (C.c_int, [I32, I64, I64, P, P, P]),
+    "pa_gather_workspace_bytes": (SZ, [PDESC, PMESH]),
+    "pa_tangent_build_gather": (C.c_int, [PDESC, P, C.c_int, PMESH, C.POINTER(Incidence), PCSR, P, P, P, P, P, SZ,
+                                          P]),
     "pa_param_backward_workspace": (SZ, [PDESC, C.c_int, I64]),
     "pa_param_backward": (C.c_int, [PDESC, P, C.c_int, I64, P, P, P, P, SZ, P]),
     "pa_profile_enable": (C.c_int, [I32]),

@@ -194,8 +194,21 @@ class FEMesh:
         L.check(lib.pa_element_csr_map(C.byref(self.c_mesh), C.byref(self.c_csr), _p(self.e2csr), _stream()),
                 "pa_element_csr_map")
         self.c_col = L.Colouring(self.n_colours, self.colour_ptr.ctypes.data_as(C.c_void_p).value, None)
+        # node incidence for the gather assembly
+        inc_ptr = np.empty(self.n_nodes + 1, dtype=np.int64)
+        inc_ent = np.empty(n_el * nen, dtype=np.int32)
+        L.check(lib.pa_node_incidence(nen, n_el, self.n_nodes, cp, inc_ptr.ctypes.data_as(C.c_void_p),
+                                      inc_ent.ctypes.data_as(C.c_void_p)), "pa_node_incidence")
+        self.inc_ptr_host, self.inc_ent_host = inc_ptr, inc_ent
+        self.inc_ptr = torch.tensor(inc_ptr, device=dev)
+        self.inc_ent = torch.tensor(inc_ent, device=dev)
+        self.max_row = int(np.diff(row_ptr).max()) if self.n_nodes else 0
+        self.c_inc = L.Incidence(self.n_nodes, n_el * nen, self.max_row, self.inc_ptr.data_ptr(),
+                                 self.inc_ent.data_ptr())
 
-    def workspace_bytes(self, model: Model) -> int:
+    def workspace_bytes(self, model: Model, assembly: str = "coloured") -> int:
+        if assembly == "gather":
+            return self.lib.pa_gather_workspace_bytes(C.byref(model.desc), C.byref(self.c_mesh))
         return self.lib.pa_element_workspace_bytes(C.byref(model.desc), C.byref(self.c_mesh))
 
 
@@ -233,12 +246,18 @@ def assemble_csr(mesh: FEMesh, r_e, K_e, r=None, vals=None, zero_first=True):
 
 
 def tangent_build(model: Model, mesh: FEMesh, u, prec="fp64", workspace=None, bufs=None, fused=True,
-                  n_bad=None):
-    """One Newton tangent build: u -> (r, CSR values).  fused=True runs
-    pa_tangent_build (element rows scattered straight into CSR); fused=False
-    runs pa_element_residual_stiffness then pa_assemble_csr."""
+                  n_bad=None, assembly="gather"):
+    """One Newton tangent build: u -> (r, CSR values).
+
+    assembly="gather" (default) runs pa_tangent_build_gather (element-major
+    tables, then one pass per node writing its CSR rows once);
+    assembly="coloured" with fused=True runs pa_tangent_build (element rows
+    scattered straight into CSR colour by colour); fused=False runs
+    pa_element_residual_stiffness then pa_assemble_csr."""
     bufs = bufs if bufs is not None else {}
-    if not fused:
+    if assembly not in ("gather", "coloured"):
+        raise ValueError(f"unknown assembly {assembly!r}")
+    if assembly == "coloured" and not fused:
         r_e, K_e = element_residual_stiffness(model, mesh, u, prec, workspace=workspace,
                                               r_e=bufs.get("r_e"), K_e=bufs.get("K_e"), n_bad=n_bad)
         r, vals = assemble_csr(mesh, r_e, K_e, r=bufs.get("r"), vals=bufs.get("vals"))
@@ -252,6 +271,16 @@ def tangent_build(model: Model, mesh: FEMesh, u, prec="fp64", workspace=None, bu
         r = torch.empty(3 * mesh.n_nodes, dtype=torch.float64, device=dev)
     if vals is None:
         vals = torch.empty(mesh.nnz, dtype=torch.float64, device=dev)
+    if assembly == "gather":
+        nb = mesh.workspace_bytes(model, "gather")
+        if workspace is None or workspace.numel() < nb:
+            workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+        L.check(model.lib.pa_tangent_build_gather(
+            C.byref(model.desc), _p(model.prepared), _prec(prec), C.byref(mesh.c_mesh), C.byref(mesh.c_inc),
+            C.byref(mesh.c_csr), _p(u), _p(r), _p(vals), _p(n_bad), _p(workspace), workspace.numel(), _stream()),
+            "pa_tangent_build_gather")
+        bufs.update(r=r, vals=vals)
+        return r, vals
     nb = mesh.workspace_bytes(model)
     if workspace is None or workspace.numel() < nb:
         workspace = torch.empty(nb, dtype=torch.uint8, device=dev)

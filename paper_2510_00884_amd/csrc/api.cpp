@@ -18,6 +18,8 @@ int host_csr_pattern(int nen, int64_t n_el, int64_t n_nodes, const int32_t* conn
                      int32_t* col, int64_t* nnz_out);
 int host_colour(int nen, int64_t n_el, int64_t n_nodes, const int32_t* conn, int32_t* colour,
                 int32_t* n_colours);
+int host_node_incidence(int nen, int64_t n_el, int64_t n_nodes, const int32_t* conn, int64_t* ptr,
+                        int32_t* ent);
 }
 
 using namespace pa;
@@ -316,7 +318,7 @@ int pa_element_residual_stiffness(const pa_model_desc* d, const void* prepared, 
   {
     Prof pr("integrate", s);
     launch_chain_integrate(m->nen, m->n_el, 0, m->n_el, m->conn, m->dNdX, m->w, F, SC, r_e, K_e, nullptr,
-                           nullptr, nullptr, nullptr, false, s);
+                           nullptr, nullptr, nullptr, 0, s);
   }
   return hip_check("pa_element_residual_stiffness");
 }
@@ -354,9 +356,69 @@ int pa_tangent_build(const pa_model_desc* d, const void* prepared, int prec, con
     Prof pr("integrate_scatter", s);
     const int64_t b = col->colour_ptr[k], cnt = col->colour_ptr[k + 1] - b;
     launch_chain_integrate(m->nen, m->n_el, b, cnt, m->conn, m->dNdX, m->w, F, SC, nullptr, nullptr, c->row_ptr,
-                           c->e2csr, r, vals, true, s);
+                           c->e2csr, r, vals, 1, s);
   }
   return hip_check("pa_tangent_build");
+}
+
+size_t pa_gather_workspace_bytes(const pa_model_desc* d, const pa_mesh* m) {
+  const size_t base = pa_element_workspace_bytes(d, m);
+  if (!base) return 0;
+  const int64_t nd = 3 * (int64_t)m->nen;
+  return (size_t)(al((int64_t)base) + al(8 * nd * m->n_el) + al(8 * nd * nd * m->n_el));
+}
+
+int pa_tangent_build_gather(const pa_model_desc* d, const void* prepared, int prec, const pa_mesh* m,
+                            const pa_incidence* inc, const pa_csr* c, const double* u, double* r, double* vals,
+                            int32_t* n_bad, void* workspace, size_t ws_bytes, void* stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if ((rc = check_prec(prec))) return rc;
+  if ((rc = check_mesh(m))) return rc;
+  if (!inc || !c) return fail(PA_ERR_ARG, "incidence and csr must be non-NULL");
+  if (inc->n_nodes != m->n_nodes || inc->n_ent != m->n_el * m->nen)
+    return fail(PA_ERR_ARG, "incidence does not match the mesh (%lld nodes, %lld entries)", (long long)inc->n_nodes,
+                (long long)inc->n_ent);
+  if (c->n_rows != 3 * m->n_nodes) return fail(PA_ERR_ARG, "csr has %lld rows, mesh needs %lld", (long long)c->n_rows, (long long)(3 * m->n_nodes));
+  if (!r && !vals) return fail(PA_ERR_ARG, "nothing to assemble");
+  if (!c->row_ptr || !c->e2csr) return fail(PA_ERR_ARG, "csr row_ptr and e2csr are needed");
+  if (m->n_nodes > 0 && (!inc->ptr || (!inc->ent && inc->n_ent > 0))) return fail(PA_ERR_ARG, "incidence arrays missing");
+  if (inc->max_row < 0 || (size_t)4 * 3 * inc->max_row * sizeof(double) > 64 * 1024)
+    return fail(PA_ERR_UNSUPPORTED, "max_row %d out of range (at most %d)", inc->max_row, 64 * 1024 / (12 * 8));
+  if (m->n_el * (int64_t)m->nen >= ((int64_t)1 << 31)) return fail(PA_ERR_ARG, "n_el * nen must fit in 31 bits");
+  if (m->n_el == 0) return PA_OK;
+  if (!prepared || !u) return fail(PA_ERR_ARG, "prepared and u must be non-NULL");
+  const int64_t need = (int64_t)pa_gather_workspace_bytes(d, m);
+  if (!workspace || (int64_t)ws_bytes < need) return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
+  hipStream_t s = S(stream);
+  double *F, *SC;
+  unsigned char* ws = (unsigned char*)workspace;
+  if ((rc = element_front(d, prepared, prec, m, u, n_bad, ws, s, &F, &SC))) return rc;
+  const int64_t nd = 3 * (int64_t)m->nen;
+  unsigned char* tab = ws + al((int64_t)pa_element_workspace_bytes(d, m));
+  double* rw = (double*)tab;
+  double* Kw = (double*)(tab + al(8 * nd * m->n_el));
+  {
+    Prof pr("integrate_elmajor", s);
+    launch_chain_integrate(m->nen, m->n_el, 0, m->n_el, m->conn, m->dNdX, m->w, F, SC, rw, Kw, nullptr, nullptr,
+                           nullptr, nullptr, 2, s);
+  }
+  {
+    Prof pr("gather_assemble", s);
+    launch_gather_assemble(m->nen, m->n_nodes, inc->ptr, inc->ent, c->row_ptr, c->e2csr, Kw, rw, r, vals,
+                           inc->max_row, s);
+  }
+  return hip_check("pa_tangent_build_gather");
+}
+
+int pa_node_incidence(int32_t nen, int64_t n_el, int64_t n_nodes, const int32_t* conn_host, int64_t* ptr,
+                      int32_t* ent) {
+  if (nen != 8 && nen != 10) return fail(PA_ERR_ARG, "nen must be 8 or 10");
+  if (!conn_host || !ptr || n_el < 0 || n_nodes < 0) return fail(PA_ERR_ARG, "bad arguments");
+  if (n_el * (int64_t)nen >= ((int64_t)1 << 31)) return fail(PA_ERR_ARG, "n_el * nen must fit in 31 bits");
+  if (host_node_incidence(nen, n_el, n_nodes, conn_host, ptr, ent))
+    return fail(PA_ERR_ARG, "connectivity refers to a node outside [0, n_nodes)");
+  return PA_OK;
 }
 
 int pa_csr_pattern(int32_t nen, int64_t n_el, int64_t n_nodes, const int32_t* conn_host, int64_t* row_ptr,

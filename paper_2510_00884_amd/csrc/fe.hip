@@ -135,10 +135,13 @@ __global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, const int32_t* _
 //    r^a_i      = sum_q w 2 (F S~ G^a)_i,                     G^a = dN^a/dX
 //    K^ab_ik    = sum_q w [2 delta_ik G^a.S~ G^b + 4 F_iI F_kK G^a_J CC~_IJKL G^b_L]
 //  i.e. the material form  sum_q w G^a_J AA_iJkL G^b_L  with AA never stored.
-// SCATTER = false writes r_e [nd][n_el] and K_e [nd][nd][n_el];
-// SCATTER = true adds the rows straight into the global r and CSR values
-// (one launch per colour, so no two threads touch the same entry).
-template <int NEN, bool SCATTER>
+// MODE 0 (tables) writes r_e [nd][n_el] and K_e [nd][nd][n_el];
+// MODE 1 (scatter) adds the rows straight into the global r and CSR values
+// (one launch per colour, so no two threads touch the same entry);
+// MODE 2 (element-major tables) writes r_e [n_el][nd] and K_e [n_el][nd][nd],
+// the layout read by the gather assembly (a node's three rows of one element
+// are contiguous).
+template <int NEN, int MODE>
 __global__ void __launch_bounds__(128) k_chain_integrate(
     int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* __restrict__ conn,
     const double* __restrict__ dNdX, const double* __restrict__ w, const double* __restrict__ F,
@@ -227,12 +230,17 @@ __global__ void __launch_bounds__(128) k_chain_integrate(
         for (int kk = 0; kk < 3; ++kk) acc[3 * b + kk] += T[kk][0] * g0 + T[kk][1] * g1 + T[kk][2] * g2;
       }
     }
-    if constexpr (!SCATTER) {
+    if constexpr (MODE == 0) {
       r_e[(int64_t)rho * n_el + e] = rr;
       if (K_e) {
 #pragma unroll
         for (int c = 0; c < ND; ++c) K_e[((int64_t)rho * ND + c) * n_el + e] = acc[c];
       }
+    } else if constexpr (MODE == 2) {
+      r_e[e * ND + rho] = rr;
+      double* dst = K_e + (e * ND + rho) * ND;
+#pragma unroll
+      for (int c = 0; c < ND; c += 2) *(double2*)(dst + c) = double2{acc[c], acc[c + 1]};
     } else {
       const int64_t R = 3 * (int64_t)conn[(int64_t)a * n_el + e] + i;
       if (r) r[R] += rr;
@@ -249,6 +257,83 @@ __global__ void __launch_bounds__(128) k_chain_integrate(
       }
     }
   }
+}
+
+// ---------------------------------------------------------------- gather assembly
+// One wave per node i: rows 3i..3i+2 of the CSR values and of r are the sums,
+// over the node's (element e, local node a) pairs in incidence order
+// (ascending e), of rows 3a..3a+2 of K_e and r_e (element-major tables).  The
+// three rows are accumulated in LDS and written once, contiguously (the rows
+// of one node share one column pattern and follow each other in CSR), so
+// every CSR value is written exactly once: no colouring, no atomics, no
+// clearing pass, bitwise reproducible.  Lane t of a round adds entry t of the
+// element's 3 x nd block; targets within one element are distinct, and the
+// LDS operations of one wave complete in issue order, so elements are summed
+// one after another.
+template <int NEN>
+__global__ void __launch_bounds__(256) k_gather_assemble(
+    int64_t n_nodes, const int64_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_ent,
+    const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ e2csr, const double* __restrict__ Kw,
+    const double* __restrict__ rw, double* __restrict__ r, double* __restrict__ vals, int max_row) {
+  constexpr int ND = 3 * NEN, NB = 3 * ND, R = (NB + 63) / 64;
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t node = (int64_t)blockIdx.x * (blockDim.x / 64) + wv;
+  if (node >= n_nodes) return;  // the whole wave leaves; the kernel has no block barrier
+  double* acc = lds + (int64_t)wv * 3 * max_row;
+  const int64_t rb = row_ptr[3 * node];
+  const int len = (int)(row_ptr[3 * node + 1] - rb);
+  if (len > max_row) return;  // caller's bound is wrong: leave the rows untouched rather than overrun LDS
+  for (int t = lane; t < 3 * len; t += 64) acc[t] = 0.0;
+  // the entry t handled by this lane in round rr: row ii, node block b, column jj
+  int tb[R], tl[R];
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr) {
+    const int t = lane + 64 * rr;
+    const int ii = t / ND, c = t % ND;
+    tb[rr] = c / 3;
+    tl[rr] = ii * len + c % 3;
+  }
+  double racc = 0.0;
+  const int64_t k0 = inc_ptr[node], k1 = inc_ptr[node + 1];
+  for (int64_t kc = k0; kc < k1; kc += 64) {
+    const int cnt = (int)((k1 - kc) < 64 ? (k1 - kc) : 64);
+    const int32_t mine = lane < cnt ? inc_ent[kc + lane] : 0;
+    double v[R];
+    int o[R];
+    auto load = [&](int j, double (&vv)[R], int (&oo)[R]) {
+      const int32_t ea = __builtin_amdgcn_readlane(mine, j);
+      const int64_t e = ea / NEN;
+      const int a = ea - (int)e * NEN;
+      const double* src = Kw + (e * ND + 3 * a) * ND;
+      const int32_t* off = e2csr + (int64_t)ea * NEN;
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int t = lane + 64 * rr;
+        if (t < NB) {
+          vv[rr] = src[t];
+          oo[rr] = off[tb[rr]];
+        }
+      }
+      if (lane < 3) racc += rw[e * ND + 3 * a + lane];
+    };
+    load(0, v, o);
+    for (int j = 0; j < cnt; ++j) {
+      double vn[R];
+      int on[R];
+      if (j + 1 < cnt) load(j + 1, vn, on);
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int t = lane + 64 * rr;
+        if (t < NB && o[rr] >= 0) acc[tl[rr] + o[rr]] += v[rr];
+      }
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) { v[rr] = vn[rr]; o[rr] = on[rr]; }
+    }
+  }
+  if (vals)
+    for (int t = lane; t < 3 * len; t += 64) vals[rb + t] = acc[t];
+  if (r && lane < 3) r[3 * node + lane] = racc;
 }
 
 // ---------------------------------------------------------------- CSR map
@@ -335,19 +420,37 @@ int launch_gather_F(int nen, int nq, int64_t n_el, const int32_t* conn, const do
 int launch_chain_integrate(int nen, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
                            const double* dNdX, const double* w, const double* F, const double* SC,
                            double* r_e, double* K_e, const int64_t* row_ptr, const int32_t* e2csr, double* r,
-                           double* vals, bool scatter, hipStream_t s) {
+                           double* vals, int mode, hipStream_t s) {
   if (e_count == 0) return 0;
-  if (nen == 8) {
-    const unsigned grid = nblocks(e_count, 16);
-    if (scatter) k_chain_integrate<8, true><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e, row_ptr, e2csr, r, vals);
-    else k_chain_integrate<8, false><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e, row_ptr, e2csr, r, vals);
-  } else if (nen == 10) {
-    const unsigned grid = nblocks(e_count, 32);
-    if (scatter) k_chain_integrate<10, true><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e, row_ptr, e2csr, r, vals);
-    else k_chain_integrate<10, false><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e, row_ptr, e2csr, r, vals);
-  } else {
-    return -1;
+#define PA_INTEGRATE(NEN_, EPB)                                                                                    \
+  {                                                                                                                \
+    const unsigned grid = nblocks(e_count, EPB);                                                                   \
+    if (mode == 1)                                                                                                 \
+      k_chain_integrate<NEN_, 1><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,      \
+                                                      row_ptr, e2csr, r, vals);                                    \
+    else if (mode == 2)                                                                                            \
+      k_chain_integrate<NEN_, 2><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,      \
+                                                      row_ptr, e2csr, r, vals);                                    \
+    else                                                                                                           \
+      k_chain_integrate<NEN_, 0><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,      \
+                                                      row_ptr, e2csr, r, vals);                                    \
   }
+  if (nen == 8) PA_INTEGRATE(8, 16)
+  else if (nen == 10) PA_INTEGRATE(10, 32)
+  else return -1;
+#undef PA_INTEGRATE
+  return 0;
+}
+
+int launch_gather_assemble(int nen, int64_t n_nodes, const int64_t* inc_ptr, const int32_t* inc_ent,
+                           const int64_t* row_ptr, const int32_t* e2csr, const double* Kw, const double* rw,
+                           double* r, double* vals, int max_row, hipStream_t s) {
+  if (n_nodes == 0) return 0;
+  const size_t lds = (size_t)4 * 3 * max_row * sizeof(double);
+  if (lds > 64 * 1024) return -1;
+  PA_NEN_SWITCH(nen,
+                (k_gather_assemble<8><<<nblocks(n_nodes, 4), 256, lds, s>>>(n_nodes, inc_ptr, inc_ent, row_ptr, e2csr, Kw, rw, r, vals, max_row)),
+                (k_gather_assemble<10><<<nblocks(n_nodes, 4), 256, lds, s>>>(n_nodes, inc_ptr, inc_ent, row_ptr, e2csr, Kw, rw, r, vals, max_row)));
   return 0;
 }
 

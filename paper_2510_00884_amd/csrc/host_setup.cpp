@@ -55,6 +55,24 @@ int host_csr_pattern(int nen, int64_t n_el, int64_t n_nodes, const int32_t* conn
   return 0;
 }
 
+// For every node, the (element, local node) pairs that touch it as e*nen + a,
+// in ascending element order (the summation order of the gather assembly).
+int host_node_incidence(int nen, int64_t n_el, int64_t n_nodes, const int32_t* conn, int64_t* ptr,
+                        int32_t* ent) {
+  for (int64_t i = 0; i < n_el * nen; ++i)
+    if (conn[i] < 0 || conn[i] >= n_nodes) return -1;
+  for (int64_t i = 0; i <= n_nodes; ++i) ptr[i] = 0;
+  for (int64_t e = 0; e < n_el; ++e)
+    for (int a = 0; a < nen; ++a) ptr[conn[e * nen + a] + 1]++;
+  for (int64_t i = 0; i < n_nodes; ++i) ptr[i + 1] += ptr[i];
+  if (ent) {
+    std::vector<int64_t> fill(ptr, ptr + n_nodes);
+    for (int64_t e = 0; e < n_el; ++e)
+      for (int a = 0; a < nen; ++a) ent[fill[conn[e * nen + a]]++] = (int32_t)(e * nen + a);
+  }
+  return 0;
+}
+
 int host_colour(int nen, int64_t n_el, int64_t n_nodes, const int32_t* conn, int32_t* colour,
                 int32_t* n_colours) {
   for (int64_t i = 0; i < n_el * nen; ++i)

@@ -75,7 +75,10 @@ int launch_gather_F(int nen, int nq, int64_t n_el, const int32_t* conn, const do
 int launch_chain_integrate(int nen, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
                            const double* dNdX, const double* w, const double* F, const double* SC,
                            double* r_e, double* K_e, const int64_t* row_ptr, const int32_t* e2csr, double* r,
-                           double* vals, bool scatter, hipStream_t s);
+                           double* vals, int mode, hipStream_t s);
+int launch_gather_assemble(int nen, int64_t n_nodes, const int64_t* inc_ptr, const int32_t* inc_ent,
+                           const int64_t* row_ptr, const int32_t* e2csr, const double* Kw, const double* rw,
+                           double* r, double* vals, int max_row, hipStream_t s);
 int launch_csr_map(int nen, int64_t n_el, const int32_t* conn, const int64_t* row_ptr,
                    const int32_t* col, int32_t* e2csr, hipStream_t s);
 int launch_assemble(int nen, int64_t e_begin, int64_t e_count, const int32_t* perm, int64_t n_el,

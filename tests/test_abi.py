@@ -120,3 +120,27 @@ def test_greedy_colouring_is_valid(lib, kind, n):
     bad[0, 0] = X.shape[0]
     assert lib.pa_colour_elements(bad.shape[1], bad.shape[0], X.shape[0], bad.ctypes.data_as(C.c_void_p),
                                   colour.ctypes.data_as(C.c_void_p), C.byref(nc)) == L.PA_ERR_ARG
+
+
+@pytest.mark.parametrize("kind,n", [("hex8", 3), ("tet10", 2)])
+def test_node_incidence(lib, kind, n):
+    """Every (element, local node) pair appears once, under its node, in
+    ascending element order."""
+    X, conn, _ = (synth.hex_mesh if kind == "hex8" else synth.tet10_mesh)(n)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    n_el, nen = conn.shape
+    ptr = np.empty(X.shape[0] + 1, dtype=np.int64)
+    ent = np.empty(n_el * nen, dtype=np.int32)
+    cp = conn.ctypes.data_as(C.c_void_p)
+    assert lib.pa_node_incidence(nen, n_el, X.shape[0], cp, ptr.ctypes.data_as(C.c_void_p),
+                                 ent.ctypes.data_as(C.c_void_p)) == 0
+    assert ptr[0] == 0 and ptr[-1] == n_el * nen
+    for i in range(X.shape[0]):
+        e, a = np.divmod(ent[ptr[i]:ptr[i + 1]], nen)
+        assert np.all(conn[e, a] == i)
+        assert np.all(np.diff(e) > 0)
+        assert ptr[i + 1] - ptr[i] == np.count_nonzero(conn == i)
+    bad = conn.copy()
+    bad[0, 0] = -1
+    assert lib.pa_node_incidence(nen, n_el, X.shape[0], bad.ctypes.data_as(C.c_void_p),
+                                 ptr.ctypes.data_as(C.c_void_p), None) == L.PA_ERR_ARG

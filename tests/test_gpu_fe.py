@@ -61,10 +61,16 @@ def test_element_residual_stiffness_and_assembly(kind, n, n_sv, h, L):
     np.testing.assert_array_equal(mesh.col_host, Kg.indices)
     close(r.cpu().numpy(), rg, 1e-12, "r.cpu().numpy()")
     close(vals.cpu().numpy(), Kg.data, 1e-12, "vals.cpu().numpy()")
-    # fused build scatters the same rows straight into CSR
-    rf, vf = api.tangent_build(gm, mesh, ut, prec="fp64", fused=True)
+    # fused coloured build scatters the same rows straight into CSR
+    rf, vf = api.tangent_build(gm, mesh, ut, prec="fp64", fused=True, assembly="coloured")
     close(rf.cpu().numpy(), rg, 1e-12, "fused r")
     close(vf.cpu().numpy(), Kg.data, 1e-12, "fused vals")
+    # node-centric gather build writes every CSR row once (poisoned buffers
+    # first: nothing may be left from before)
+    bufs = {"r": torch.full_like(rf, float("nan")), "vals": torch.full_like(vf, float("nan"))}
+    rgt, vgt = api.tangent_build(gm, mesh, ut, prec="fp64", assembly="gather", bufs=bufs)
+    close(rgt.cpu().numpy(), rg, 1e-12, "gather r")
+    close(vgt.cpu().numpy(), Kg.data, 1e-12, "gather vals")
 
 
 def test_assembly_greedy_colouring_and_determinism():
@@ -72,14 +78,19 @@ def test_assembly_greedy_colouring_and_determinism():
     say("assembly greedy colouring")
     X, conn, gm, om, mesh, u = setup(api, "hex8", 4, colour="greedy")
     ut = torch.tensor(u, device="cuda")
-    r1, v1 = api.tangent_build(gm, mesh, ut, fused=False)
+    r1, v1 = api.tangent_build(gm, mesh, ut, fused=False, assembly="coloured")
     r1, v1 = r1.clone(), v1.clone()
-    r2, v2 = api.tangent_build(gm, mesh, ut, fused=False)
+    r2, v2 = api.tangent_build(gm, mesh, ut, fused=False, assembly="coloured")
     assert torch.equal(r1, r2) and torch.equal(v1, v2)   # fixed colouring: bitwise deterministic
-    r3, v3 = api.tangent_build(gm, mesh, ut, fused=True)
+    r3, v3 = api.tangent_build(gm, mesh, ut, fused=True, assembly="coloured")
     r3, v3 = r3.clone(), v3.clone()
-    r4, v4 = api.tangent_build(gm, mesh, ut, fused=True)
+    r4, v4 = api.tangent_build(gm, mesh, ut, fused=True, assembly="coloured")
     assert torch.equal(r3, r4) and torch.equal(v3, v4)
+    r5, v5 = api.tangent_build(gm, mesh, ut, assembly="gather")
+    r5, v5 = r5.clone(), v5.clone()
+    r6, v6 = api.tangent_build(gm, mesh, ut, assembly="gather")
+    assert torch.equal(r5, r6) and torch.equal(v5, v6)   # incidence order: bitwise deterministic
+    close(v5.cpu().numpy(), v1.cpu().numpy(), 1e-14, "gather vs coloured")
     cperm = conn[mesh.perm]
     dNdX, w, _ = fe.geometry(X, cperm)
     r_ref, K_ref, _ = fe.element_residual_stiffness(u, cperm, dNdX, w, om)
@@ -114,6 +125,7 @@ def test_tangent_build_adjoint_hessian(kind, n, n_sv, h, L):
     dNdX, w, _ = fe.geometry(X, cperm)
     r_ref, K_ref, _ = fe.element_residual_stiffness(u, cperm, dNdX, w, om)
     rg, Kg = fe.assemble(cperm, r_ref, K_ref, X.shape[0])
-    rf, vf = api.tangent_build(gm, mesh, torch.tensor(u, device="cuda"), prec="fp64")
-    close(rf.cpu().numpy(), rg, 1e-12, "r")
-    close(vf.cpu().numpy(), Kg.data, 1e-12, "vals")
+    for assembly in ("gather", "coloured"):
+        rf, vf = api.tangent_build(gm, mesh, torch.tensor(u, device="cuda"), prec="fp64", assembly=assembly)
+        close(rf.cpu().numpy(), rg, 1e-12, f"r ({assembly})")
+        close(vf.cpu().numpy(), Kg.data, 1e-12, f"vals ({assembly})")
