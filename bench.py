@@ -114,6 +114,9 @@ def main():
                     help="network Hessian formation (BF16 variants always use forward)")
     ap.add_argument("--variants", default="fp32,bf16,bf16_corr",
                     help="other precisions timed after the headline run ('' for none)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB mebibytes three times (the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="elements in the oracle CPU sample (0: skip)")
     ap.add_argument("--assembly", default="gather", choices=["gather", "coloured", "tables"],
                     help="gather: element-major tables + one pass per node (default); coloured: element rows "
@@ -133,6 +136,15 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        nb = args.copy_probe << 20
+        x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nb, "copy_probe_bytes_written": nb, "launches": 3}), flush=True)
+        return
     n = args.n
     n_sv, h, Lh = 2, 32, 2
     p = synth.num_inputs(n_sv)
@@ -223,7 +235,7 @@ def main():
                     "frac": ach / HBM_PEAK, "traffic": None, "kernel": dom}
 
     variants = {}
-    for vp in [x for x in args.variants.split(",") if x and x != args.prec]:
+    for vp in [x for x in args.variants.split(",") if x and x not in ("none", args.prec)]:
         # the adjoint-form Hessian has FP64 and FP32 kernels only
         model.algorithm = args.algo if vp in ("fp64", "fp32") else "forward"
         vms, vk = run(vp, max(args.steps // 2, 2), 1, True)

@@ -586,6 +586,7 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   __shared__ T W1s[P][H];
   __shared__ double outp[NW][NOUT][16];
   __shared__ T xbuf[CH][H][16];
+  __shared__ T l1buf[2][H][16];
 
   const bool dbl = std::is_same<T, double>::value;
   const T* t_W1t = (const T*)(prep + (dbl ? lay.d_W1t : lay.f_W1t));
@@ -605,19 +606,21 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     const int m = 4 * s + g;
     kB[s] = (valid && m < P) ? (T)Kin[(int64_t)m * n + qp] : (T)0;
   }
-  // layer 1, all rows
-  T s1[MB][4], t1[MB][4], z1[MB][4];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
+  // layer 1: own rows, then z_1 and F'(y_1) of every row through LDS
+  T t1w[4], z1[MB][4];
+  {
     typename E::frag a1[S1];
 #pragma unroll
-    for (int s = 0; s < S1; ++s) a1[s] = fW1[(mb * S1 + s) * 64 + lane];
+    for (int s = 0; s < S1; ++s) a1[s] = fW1[(w * S1 + s) * 64 + lane];
     acc_t acc = mma_in<E, P>(a1, kB, zero_acc<E>());
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       T f, f1, f2;
-      softplus3((T)(acc[v] + t_c[16 * mb + E::row(g, v)]), f, f1, f2);
-      z1[mb][v] = f; s1[mb][v] = f1; t1[mb][v] = f2;
+      const int r = 16 * w + E::row(g, v);
+      softplus3((T)(acc[v] + t_c[r]), f, f1, f2);
+      t1w[v] = f2;
+      l1buf[0][r][q] = f;
+      l1buf[1][r][q] = f1;
     }
   }
   typename E::frag AV[L - 1][SH], BV[L - 1][S1];
@@ -631,7 +634,13 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   T a_own[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) a_own[v] = t_a[16 * w + E::row(g, v)];
-  __syncthreads();  // W1s
+  __syncthreads();  // W1s, l1buf
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      z1[mb][v] = l1buf[0][16 * mb + E::row(g, v)][q];
+    }
 
   // ---- 1. value forward (own rows of layers 2..L)
   T sk[L - 1][4], tk[L - 1][4];
@@ -699,30 +708,39 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
           gam[k - 2][v] = l * tk[k - 3][v];
           mu[v] = l * sk[k - 3][v];
         } else {
-          gam[0][v] = l * t1[w][v];
+          gam[0][v] = l * t1w[v];
         }
       }
     });
     __syncthreads();  // xbuf free
   }
 
-  // ---- 3. Jacobian forward with the Gram sums
-  T Hp[P2];
-#pragma unroll
-  for (int h = 0; h < P2; ++h) Hp[h] = (T)0;
-  if (hess) {  // layer 1: J_1 = W1 (own rows of block w)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * w + E::row(g, v);
-      T wr[P];
-#pragma unroll
-      for (int m = 0; m < P; ++m) wr[m] = W1s[m][r];
-      static_for<P2>([&](auto HI) {
-        constexpr int h = decltype(HI)::value;
+  // ---- 3. Jacobian forward with the Gram sums.  Each layer's sum over the
+  // wave's 16 rows is reduced four pairs at a time (reduce4) and added into
+  // outp, so no per-lane Hessian partials stay live across layers.
+  // gram(layer, col): adds sum_rows gamma_layer * col(m) * col(n) for every pair.
+  auto gram = [&](const T (&gm)[4], auto colv, bool first) {
+    static_for<(P2 + 3) / 4>([&](auto BI) {
+      constexpr int c0 = decltype(BI)::value * 4;
+      double pp[4];
+      static_for<4>([&](auto JI) {
+        constexpr int j = decltype(JI)::value;
+        constexpr int h = (c0 + j < P2) ? c0 + j : 0;
         constexpr int m = hess_m(h, P), nn = hess_n(h, P);
-        Hp[h] += gam[0][v] * wr[m] * wr[nn];
+        T x = (T)0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x += gm[v] * colv(m, v) * colv(nn, v);
+        pp[j] = (c0 + j < P2) ? (double)x : 0.0;
       });
-    }
+      const double r = reduce4(pp[0], pp[1], pp[2], pp[3], g);
+      if (c0 + g < P2) {
+        double& o = outp[w][1 + P + c0 + g][q];
+        o = first ? r : o + r;
+      }
+    });
+  };
+  if (hess) {  // layer 1: J_1 = W1 (own rows of block w)
+    gram(gam[0], [&](int m, int v) { return W1s[m][16 * w + E::row(g, v)]; }, true);
   }
   T J[P][4];  // dy_k/dK_m, own rows of the current layer
   static_for<L - 1>([&](auto KI) {
@@ -734,7 +752,10 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) src[mb][v] = s1[mb][v] * W1s[m][16 * mb + E::row(g, v)];
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * mb + E::row(g, v);
+            src[mb][v] = l1buf[1][r][q] * W1s[m][r];
+          }
         acc_t acc = mma_src<E, MB>(AV[0], src, zero_acc<E>());
 #pragma unroll
         for (int v = 0; v < 4; ++v) J[m][v] = (T)acc[v] + t_Bt[((int64_t)1 * P + m) * H + 16 * w + E::row(g, v)];
@@ -768,15 +789,7 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
         });
       });
     }
-    if (hess) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        static_for<P2>([&](auto HI) {
-          constexpr int h = decltype(HI)::value;
-          constexpr int m = hess_m(h, P), nn = hess_n(h, P);
-          Hp[h] += gam[k - 1][v] * J[m][v] * J[nn][v];
-        });
-    }
+    if (hess) gram(gam[k - 1], [&](int m, int v) { return J[m][v]; }, false);
   });
   // gradient outputs: dN/dK_m = sum_j a_j F'(y_L,j) J_L[j, m] (+ b_m below)
   static_for<(P + 3) / 4>([&](auto BI) {
@@ -794,17 +807,6 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     const double r = reduce4(pp[0], pp[1], pp[2], pp[3], g);
     if (c0 + g < P) outp[w][1 + c0 + g][q] = r;
   });
-  if (hess) {
-    static_for<(P2 + 3) / 4>([&](auto BI) {
-      constexpr int c0 = decltype(BI)::value * 4;
-      double pp[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) pp[j] = (c0 + j < P2) ? (double)Hp[c0 + j < P2 ? c0 + j : 0] : 0.0;
-      const double r = reduce4(pp[0], pp[1], pp[2], pp[3], g);
-      if (c0 + g < P2) outp[w][1 + P + c0 + g][q] = r;
-    });
-  }
-
   __syncthreads();
   const int nout_written = hess ? NOUT : 1 + P;
   for (int i = tid; i < nout_written * 16; i += 64 * NW) {

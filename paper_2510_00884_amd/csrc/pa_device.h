@@ -64,19 +64,70 @@ struct EngBF16 {
 //   F'(y)  = sigma(y)
 //   F''(y) = sigma(y) sigma(-y) = e^{-|y|} / (1 + e^{-|y|})^2
 // ---------------------------------------------------------------------------
+// a / d for d in [1, 3]: hardware reciprocal estimate, two Newton steps and
+// a residual correction of the quotient (no range scaling is needed).
+__device__ inline double div_unit(double a, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  const double q = a * r;
+  return fma(fma(-d, q, a), r, q);
+}
+__device__ inline float div_unit(float a, float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  r = fmaf(fmaf(-d, r, 1.0f), r, r);
+  const float q = a * r;
+  return fmaf(fmaf(-d, q, a), r, q);
+}
+
+// log(1 + x) for x in [0, 1] (here x = e^{-|y|}).  For x above sqrt(2) - 1,
+// log(1 + x) = ln 2 + log(1 + g) with g = (x - 1)/2 in (-0.293, 0]; then
+// log(1 + g) = 2 atanh(s), s = g / (2 + g), |s| <= 0.1716, summed as the odd
+// series 2 s sum_k s^{2k} / (2k + 1).  Terms to k = 9 (FP64) or k = 4 (FP32)
+// leave a truncation below half an ulp.
+__device__ inline double log1p_unit(double x) {
+  const bool hi = x > 0.41421356237309503;
+  const double g = hi ? 0.5 * (x - 1.0) : x;
+  const double s = div_unit(g, 2.0 + g);
+  const double s2 = s * s;
+  double p = 1.0 / 19.0;
+  p = fma(p, s2, 1.0 / 17.0);
+  p = fma(p, s2, 1.0 / 15.0);
+  p = fma(p, s2, 1.0 / 13.0);
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  const double t = 2.0 * s;
+  const double r = fma(t * s2, p, t);
+  return hi ? 0.6931471805599453 + r : r;
+}
+__device__ inline float log1p_unit(float x) {
+  const bool hi = x > 0.41421356f;
+  const float g = hi ? 0.5f * (x - 1.0f) : x;
+  const float s = div_unit(g, 2.0f + g);
+  const float s2 = s * s;
+  float p = 1.0f / 9.0f;
+  p = fmaf(p, s2, 1.0f / 7.0f);
+  p = fmaf(p, s2, 1.0f / 5.0f);
+  p = fmaf(p, s2, 1.0f / 3.0f);
+  const float t = 2.0f * s;
+  const float r = fmaf(t * s2, p, t);
+  return hi ? 0.69314718f + r : r;
+}
+
 __device__ inline void softplus3(double y, double& f, double& f1, double& f2) {
   const double e = exp(-fabs(y));
-  const double d = 1.0 + e;
-  const double r = 1.0 / d;
-  f = fmax(y, 0.0) + log1p(e);
+  const double r = div_unit(1.0, 1.0 + e);
+  f = fmax(y, 0.0) + log1p_unit(e);
   f1 = (y >= 0.0) ? r : e * r;
   f2 = e * r * r;
 }
 __device__ inline void softplus3(float y, float& f, float& f1, float& f2) {
   const float e = expf(-fabsf(y));
-  const float d = 1.0f + e;
-  const float r = 1.0f / d;
-  f = fmaxf(y, 0.0f) + log1pf(e);
+  const float r = div_unit(1.0f, 1.0f + e);
+  f = fmaxf(y, 0.0f) + log1p_unit(e);
   f1 = (y >= 0.0f) ? r : e * r;
   f2 = e * r * r;
 }
