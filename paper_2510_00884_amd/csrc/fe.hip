@@ -128,21 +128,27 @@ __global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, const int32_t* _
 }
 
 // ---------------------------------------------------------------- chain rule + integration
-// Element kernel over a block of E elements (E * NQ = 128 points):
-//  phase A, one thread per point: F, S~ = dPsi/dC, CC~ = d2Psi/dCdC (tensor
-//    components, formed per point by the material kernel) and w into LDS;
-//  phase B, one thread per (element, element row 3a+i):
-//    r^a_i      = sum_q w 2 (F S~ G^a)_i,                     G^a = dN^a/dX
-//    K^ab_ik    = sum_q w [2 delta_ik G^a.S~ G^b + 4 F_iI F_kK G^a_J CC~_IJKL G^b_L]
+// Element kernel over a block of E = 8 elements, one thread per element row
+// rho = 3a + i (E * 3 nen threads):
+//  phase A: F, S~ = dPsi/dC, CC~ = d2Psi/dCdC (tensor components, formed per
+//    point by the material kernel) and w of the block's E * nq points into
+//    LDS, coalesced (point index q * n_el + e);
+//  phase B: for every point q, with the shape gradients of q staged in LDS
+//    (the next point's are fetched while q is computed, double buffered):
+//    r^a_i      += w 2 (F S~ G^a)_i,                     G^a = dN^a/dX
+//    K^ab_ik    += w [2 delta_ik G^a.S~ G^b + 4 F_iI F_kK G^a_J CC~_IJKL G^b_L]
 //  i.e. the material form  sum_q w G^a_J AA_iJkL G^b_L  with AA never stored.
-// MODE 0 (tables) writes r_e [nd][n_el] and K_e [nd][nd][n_el];
-// MODE 1 (scatter) adds the rows straight into the global r and CSR values
-// (one launch per colour, so no two threads touch the same entry);
-// MODE 2 (element-major tables) writes r_e [n_el][nd] and K_e [n_el][nd][nd],
-// the layout read by the gather assembly (a node's three rows of one element
-// are contiguous).
+// MODE 0 (tables) writes r_e [nd][n_el] and K_e [nd][nd][n_el] (threads
+// element-fastest for coalesced stores); MODE 1 (scatter) adds the rows
+// straight into the global r and CSR values (one launch per colour, so no
+// two threads touch the same entry); MODE 2 (element-major tables) writes
+// r_e [n_el][nd] and K_e [n_el][nd][nd], the layout read by the gather
+// assembly.  MODE 1 and 2 order threads row-fastest.
+template <int NEN>
+__host__ __device__ constexpr int integrate_threads() { return 8 * 3 * NEN; }
+
 template <int NEN, int MODE>
-__global__ void __launch_bounds__(128) k_chain_integrate(
+__global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
     int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* __restrict__ conn,
     const double* __restrict__ dNdX, const double* __restrict__ w, const double* __restrict__ F,
     const double* __restrict__ SC, double* __restrict__ r_e, double* __restrict__ K_e,
@@ -150,110 +156,136 @@ __global__ void __launch_bounds__(128) k_chain_integrate(
     double* __restrict__ vals) {
   constexpr int NQ = nq_of<NEN>();
   constexpr int ND = 3 * NEN;
-  constexpr int NT = 128;
-  constexpr int E = NT / NQ;  // elements per block
-  __shared__ double sF[9][NT], sS[6][NT], sC[21][NT], sW[NT];
+  constexpr int E = 8;
+  constexpr int NT = integrate_threads<NEN>();
+  constexpr int NPT = E * NQ;  // points per block
+  constexpr int NG = E * NEN * 3;  // shape-gradient values per point slice
+  static_assert(NG == NT, "one shape-gradient value per thread per point");
+  __shared__ double sF[9][NPT], sS[6][NPT], sC[21][NPT], sW[NPT];
+  __shared__ double sG[2][NEN][3][E];
   const int tid = threadIdx.x;
   const int64_t eb = e_begin + (int64_t)blockIdx.x * E;
+  const int64_t e_end = e_begin + e_count;
   const int64_t n = n_el * NQ;
-  {  // phase A: point (q, le)
-    const int le = tid % E, q = tid / E;
-    const int64_t e = eb + le;
-    if (e < e_begin + e_count) {
-      const int64_t pt = (int64_t)q * n_el + e;
+  // phase A: every thread loads a share of the (component, point) pairs, so
+  // the block's loads are all in flight at once; point t = q * E + le
+  {
+    constexpr int NLD = (37 * NPT + NT - 1) / NT;
+    double v[NLD];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) sF[c][tid] = F[(int64_t)c * n + pt];
+    for (int k = 0; k < NLD; ++k) {  // all loads issued before any is used
+      const int idx = tid + k * NT;
+      const int c = idx / NPT, t = idx % NPT;
+      const int64_t e = eb + t % E;
+      const int64_t pt = (int64_t)(t / E) * n_el + e;
+      v[k] = 0.0;
+      if (idx < 37 * NPT && e < e_end)
+        v[k] = (c < 9) ? F[(int64_t)c * n + pt] : (c < 36) ? SC[(int64_t)(c - 9) * n + pt] : w[pt];
+    }
 #pragma unroll
-      for (int c = 0; c < 6; ++c) sS[c][tid] = SC[(int64_t)c * n + pt];
-#pragma unroll
-      for (int c = 0; c < 21; ++c) sC[c][tid] = SC[(int64_t)(6 + c) * n + pt];
-      sW[tid] = w[pt];
+    for (int k = 0; k < NLD; ++k) {
+      const int idx = tid + k * NT;
+      if (idx >= 37 * NPT) break;
+      const int c = idx / NPT, t = idx % NPT;
+      if (c < 9) sF[c][t] = v[k];
+      else if (c < 15) sS[c - 9][t] = v[k];
+      else if (c < 36) sC[c - 15][t] = v[k];
+      else sW[t] = v[k];
     }
   }
+  // this thread's shape-gradient value of every point slice: (b, J, le)
+  const int g_le = tid % E, g_J = (tid / E) % 3, g_b = tid / (3 * E);
+  const int64_t g_e = eb + g_le;
+  auto load_g = [&](int q) -> double {
+    return (g_e < e_end) ? dNdX[(((int64_t)q * NEN + g_b) * 3 + g_J) * n_el + g_e] : 0.0;
+  };
+  sG[0][g_b][g_J][g_le] = load_g(0);
   __syncthreads();
-  // phase B: (element le, row rho = 3a + i), element fastest
-  for (int idx = tid; idx < E * ND; idx += NT) {
-    const int le = idx % E, rho = idx / E;
-    const int a = rho / 3, i = rho % 3;
-    const int64_t e = eb + le;
-    if (e >= e_begin + e_count) continue;
-    double acc[ND];
+
+  // phase B: (element le, row rho = 3a + i)
+  const int le = (MODE == 0) ? tid % E : tid / ND;
+  const int rho = (MODE == 0) ? tid / E : tid % ND;
+  const int a = rho / 3, i = rho % 3;
+  const int64_t e = eb + le;
+  double acc[ND];
 #pragma unroll
-    for (int c = 0; c < ND; ++c) acc[c] = 0.0;
-    double rr = 0.0;
+  for (int c = 0; c < ND; ++c) acc[c] = 0.0;
+  double rr = 0.0;
 #pragma unroll 1
-    for (int q = 0; q < NQ; ++q) {
-      const int lq = q * E + le;
-      double ga[3];
+  for (int q = 0; q < NQ; ++q) {
+    const int buf = q & 1;
+    const double gnext = (q + 1 < NQ) ? load_g(q + 1) : 0.0;  // in flight during this point
+    const int lq = q * E + le;
+    double ga[3];
 #pragma unroll
-      for (int J = 0; J < 3; ++J) ga[J] = dNdX[(((int64_t)q * NEN + a) * 3 + J) * n_el + e];
-      const double wq = sW[lq];
-      double Fi[3];  // row i of F
+    for (int J = 0; J < 3; ++J) ga[J] = sG[buf][a][J][le];
+    const double wq = sW[lq];
+    double Fi[3];  // row i of F
 #pragma unroll
-      for (int I = 0; I < 3; ++I) Fi[I] = sF[3 * i + I][lq];
-      double Sg[3];  // S~ G^a
+    for (int I = 0; I < 3; ++I) Fi[I] = sF[3 * i + I][lq];
+    double Sg[3];  // S~ G^a
 #pragma unroll
-      for (int I = 0; I < 3; ++I) Sg[I] = sS[VI(I, 0)][lq] * ga[0] + sS[VI(I, 1)][lq] * ga[1] + sS[VI(I, 2)][lq] * ga[2];
-      rr += wq * 2.0 * (Fi[0] * Sg[0] + Fi[1] * Sg[1] + Fi[2] * Sg[2]);
-      // Wv_KL = sum_I F_iI sum_J G^a_J CC~_IJKL   (row i only)
-      double Wv[3][3];
+    for (int I = 0; I < 3; ++I) Sg[I] = sS[VI(I, 0)][lq] * ga[0] + sS[VI(I, 1)][lq] * ga[1] + sS[VI(I, 2)][lq] * ga[2];
+    rr += wq * 2.0 * (Fi[0] * Sg[0] + Fi[1] * Sg[1] + Fi[2] * Sg[2]);
+    // Wv_KL = sum_I F_iI sum_J G^a_J CC~_IJKL   (row i only)
+    double Wv[3][3];
 #pragma unroll
-      for (int K = 0; K < 3; ++K)
+    for (int K = 0; K < 3; ++K)
 #pragma unroll
-        for (int L = 0; L < 3; ++L) {
-          double s = 0.0;
+      for (int L = 0; L < 3; ++L) {
+        double s = 0.0;
 #pragma unroll
-          for (int I = 0; I < 3; ++I) {
-            double v = 0.0;
+        for (int I = 0; I < 3; ++I) {
+          double v = 0.0;
 #pragma unroll
-            for (int J = 0; J < 3; ++J) v += ga[J] * sC[TRI(VI(I, J), VI(K, L))][lq];
-            s += Fi[I] * v;
-          }
-          Wv[K][L] = s;
+          for (int J = 0; J < 3; ++J) v += ga[J] * sC[TRI(VI(I, J), VI(K, L))][lq];
+          s += Fi[I] * v;
         }
-      // T_kL = 4 sum_K F_kK Wv_KL + 2 delta_ik (S~ G^a)_L, scaled by w
-      double T[3][3];
+        Wv[K][L] = s;
+      }
+    // T_kL = 4 sum_K F_kK Wv_KL + 2 delta_ik (S~ G^a)_L, scaled by w
+    double T[3][3];
 #pragma unroll
-      for (int kk = 0; kk < 3; ++kk)
+    for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
-        for (int L = 0; L < 3; ++L) {
-          double s = sF[3 * kk][lq] * Wv[0][L] + sF[3 * kk + 1][lq] * Wv[1][L] + sF[3 * kk + 2][lq] * Wv[2][L];
-          s = 4.0 * s + (kk == i ? 2.0 * Sg[L] : 0.0);
-          T[kk][L] = wq * s;
-        }
+      for (int L = 0; L < 3; ++L) {
+        double s = sF[3 * kk][lq] * Wv[0][L] + sF[3 * kk + 1][lq] * Wv[1][L] + sF[3 * kk + 2][lq] * Wv[2][L];
+        s = 4.0 * s + (kk == i ? 2.0 * Sg[L] : 0.0);
+        T[kk][L] = wq * s;
+      }
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) {
+      const double g0 = sG[buf][b][0][le], g1 = sG[buf][b][1][le], g2 = sG[buf][b][2][le];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) acc[3 * b + kk] += T[kk][0] * g0 + T[kk][1] * g1 + T[kk][2] * g2;
+    }
+    if (q + 1 < NQ) sG[buf ^ 1][g_b][g_J][g_le] = gnext;
+    __syncthreads();
+  }
+  if (e >= e_end) return;
+  if constexpr (MODE == 0) {
+    r_e[(int64_t)rho * n_el + e] = rr;
+    if (K_e) {
+#pragma unroll
+      for (int c = 0; c < ND; ++c) K_e[((int64_t)rho * ND + c) * n_el + e] = acc[c];
+    }
+  } else if constexpr (MODE == 2) {
+    r_e[e * ND + rho] = rr;
+    double* dst = K_e + (e * ND + rho) * ND;
+#pragma unroll
+    for (int c = 0; c < ND; c += 2) *(double2*)(dst + c) = double2{acc[c], acc[c + 1]};
+  } else {
+    const int64_t R = 3 * (int64_t)conn[(int64_t)a * n_el + e] + i;
+    if (r) r[R] += rr;
+    if (vals) {
+      const int64_t base = row_ptr[R];
 #pragma unroll
       for (int b = 0; b < NEN; ++b) {
-        const double g0 = dNdX[(((int64_t)q * NEN + b) * 3 + 0) * n_el + e];
-        const double g1 = dNdX[(((int64_t)q * NEN + b) * 3 + 1) * n_el + e];
-        const double g2 = dNdX[(((int64_t)q * NEN + b) * 3 + 2) * n_el + e];
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) acc[3 * b + kk] += T[kk][0] * g0 + T[kk][1] * g1 + T[kk][2] * g2;
-      }
-    }
-    if constexpr (MODE == 0) {
-      r_e[(int64_t)rho * n_el + e] = rr;
-      if (K_e) {
-#pragma unroll
-        for (int c = 0; c < ND; ++c) K_e[((int64_t)rho * ND + c) * n_el + e] = acc[c];
-      }
-    } else if constexpr (MODE == 2) {
-      r_e[e * ND + rho] = rr;
-      double* dst = K_e + (e * ND + rho) * ND;
-#pragma unroll
-      for (int c = 0; c < ND; c += 2) *(double2*)(dst + c) = double2{acc[c], acc[c + 1]};
-    } else {
-      const int64_t R = 3 * (int64_t)conn[(int64_t)a * n_el + e] + i;
-      if (r) r[R] += rr;
-      if (vals) {
-        const int64_t base = row_ptr[R];
-#pragma unroll
-        for (int b = 0; b < NEN; ++b) {
-          const int32_t off = e2csr[(e * NEN + a) * NEN + b];
-          if (off < 0) continue;
-          vals[base + off] += acc[3 * b];
-          vals[base + off + 1] += acc[3 * b + 1];
-          vals[base + off + 2] += acc[3 * b + 2];
-        }
+        const int32_t off = e2csr[(e * NEN + a) * NEN + b];
+        if (off < 0) continue;
+        vals[base + off] += acc[3 * b];
+        vals[base + off + 1] += acc[3 * b + 1];
+        vals[base + off + 2] += acc[3 * b + 2];
       }
     }
   }
@@ -422,21 +454,22 @@ int launch_chain_integrate(int nen, int64_t n_el, int64_t e_begin, int64_t e_cou
                            double* r_e, double* K_e, const int64_t* row_ptr, const int32_t* e2csr, double* r,
                            double* vals, int mode, hipStream_t s) {
   if (e_count == 0) return 0;
-#define PA_INTEGRATE(NEN_, EPB)                                                                                    \
+#define PA_INTEGRATE(NEN_)                                                                                          \
   {                                                                                                                \
-    const unsigned grid = nblocks(e_count, EPB);                                                                   \
+    const unsigned grid = nblocks(e_count, 8);                                                                     \
+    constexpr int nt = integrate_threads<NEN_>();                                                                  \
     if (mode == 1)                                                                                                 \
-      k_chain_integrate<NEN_, 1><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,      \
-                                                      row_ptr, e2csr, r, vals);                                    \
+      k_chain_integrate<NEN_, 1><<<grid, nt, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,       \
+                                                     row_ptr, e2csr, r, vals);                                     \
     else if (mode == 2)                                                                                            \
-      k_chain_integrate<NEN_, 2><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,      \
-                                                      row_ptr, e2csr, r, vals);                                    \
+      k_chain_integrate<NEN_, 2><<<grid, nt, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,       \
+                                                     row_ptr, e2csr, r, vals);                                     \
     else                                                                                                           \
-      k_chain_integrate<NEN_, 0><<<grid, 128, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,      \
-                                                      row_ptr, e2csr, r, vals);                                    \
+      k_chain_integrate<NEN_, 0><<<grid, nt, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,       \
+                                                     row_ptr, e2csr, r, vals);                                     \
   }
-  if (nen == 8) PA_INTEGRATE(8, 16)
-  else if (nen == 10) PA_INTEGRATE(10, 32)
+  if (nen == 8) PA_INTEGRATE(8)
+  else if (nen == 10) PA_INTEGRATE(10)
   else return -1;
 #undef PA_INTEGRATE
   return 0;

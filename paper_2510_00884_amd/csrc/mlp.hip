@@ -63,6 +63,11 @@ PrepLayout prep_layout(int H, int L, int P) {
   l.z_B = take(16 * (int64_t)L * l.MB * 64);
   l.x_AT = take(8 * (int64_t)L * l.MB * l.SH * 64);
   l.y_AT = take(4 * (int64_t)L * l.MB * l.SH * 64);
+  {
+    const int npb = (P * (P + 1) / 2 + 15) / 16;
+    l.x_G1 = take(8 * (int64_t)npb * l.MB * 4 * 64);
+    l.y_G1 = take(4 * (int64_t)npb * l.MB * 4 * 64);
+  }
   l.k0 = take(8 * (int64_t)P * 16);
   l.nout = take(8 * (int64_t)l.NOUT * 16);
   l.total = o;
@@ -165,9 +170,30 @@ __global__ void k_prep_frags(const double* __restrict__ th, ThetaLayout t, PrepL
   const int64_t nAT = (int64_t)L * MB * SH * 64;
   double* xAT = (double*)(prep + l.x_AT);
   float* yAT = (float*)(prep + l.y_AT);
-  const int64_t total = nW1 + nA + nB + nzW1 + nzA + nzB + nAT;
+  const int P2 = P * (P + 1) / 2, NPB = (P2 + 15) / 16;
+  const int64_t nG1 = (int64_t)NPB * MB * 4 * 64;
+  double* xG1 = (double*)(prep + l.x_G1);
+  float* yG1 = (float*)(prep + l.y_G1);
+  const int64_t total = nW1 + nA + nB + nzW1 + nzA + nzB + nAT + nG1;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = idx;
+    if (j >= total - nG1) {  // [pb][w][s][lane]: W1_rm W1_rn, pair 16 pb + i, row 16w + row(g, s)
+      j -= total - nG1;
+      const int lane = (int)(j % 64), s = (int)((j / 64) % 4);
+      const int w = (int)((j / 256) % MB), pb = (int)(j / (256 * MB));
+      const int i = lane & 15, g = lane >> 4, pair = 16 * pb + i;
+      double v64 = 0.0, v32 = 0.0;
+      if (pair < P2) {
+        int h = pair, m = 0;
+        while (h >= P - m) { h -= P - m; ++m; }
+        const int nn = m + h;
+        const int r64 = 16 * w + row64(g, s), r32 = 16 * w + row32(g, s);
+        v64 = th_w(th, t, 1, r64, m) * th_w(th, t, 1, r64, nn);
+        v32 = th_w(th, t, 1, r32, m) * th_w(th, t, 1, r32, nn);
+      }
+      xG1[j] = v64; yG1[j] = (float)v32;
+      continue;
+    }
     if (j < nW1) {  // [mb][s][lane]: W1[16mb + i][4s + g]
       const int lane = (int)(j % 64), s = (int)((j / 64) % S1), mb = (int)(j / (64 * S1));
       const int i = lane & 15, g = lane >> 4, col = 4 * s + g;
@@ -564,29 +590,46 @@ k_mlp_fwd(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 // lambda_{k-1} = A_k^T (lambda_k (.) F'(y_k)),
 // because every second derivative of N enters through the curvature of an
 // activation (the layers are affine).  Passes per tile:
-//   1. value forward (all layers), 2. reverse sweep for lambda_k (one column,
-//   products with A_k^T), 3. Jacobian forward (p columns) accumulating the
-//   Gram sums layer by layer, so only one layer of J is live at a time.
+//   1. value forward (all layers);
+//   2. reverse sweep for gamma_k = lambda_k (.) F''(y_k) (one column,
+//      products with A_k^T);
+//   3. layer 1: J_1 = W1 is constant, so its Gram sum is the matrix product
+//      of the prepared table W1_rm W1_rn (pairs x rows) with gamma_1 (rows x
+//      points) on the matrix cores;
+//   4. Jacobian forward (p columns) for layers 2..L; each column's Gram
+//      pairs (n <= m) are summed in registers as soon as the column is
+//      formed, so the vector work overlaps the next column's matrix
+//      products, and reduced four pairs at a time into the output tile.
 // Points on the N dimension, neurons split across waves as in k_mlp_fwd.
-template <int H, int L, int P, int PR>
+// Pair t of the column-major upper triangle (m = column, n <= m).
+__host__ __device__ constexpr int colmaj_m(int t) {
+  int m = 0;
+  while (t > m) { t -= m + 1; ++m; }
+  return m;
+}
+__host__ __device__ constexpr int colmaj_n(int t) { return t - colmaj_m(t) * (colmaj_m(t) + 1) / 2; }
+// Packed row-major index of pair (n, m), n <= m.
+__host__ __device__ constexpr int packed_index(int n, int m, int P) { return n * P - n * (n - 1) / 2 + (m - n); }
+
+template <int H, int L, int P, int PR, bool HESS>
 __global__ void __launch_bounds__(64 * (H / 16))
 k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
-          const double* __restrict__ Kin, double* __restrict__ out, int hess) {
+          const double* __restrict__ Kin, double* __restrict__ out) {
   using E = typename std::conditional<PR == PREC_F64, EngF64, EngF32>::type;
   using T = typename E::T;
   using acc_t = typename E::acc;
+  using frag_t = typename E::frag;
   constexpr int MB = H / 16, NW = MB, P2 = P * (P + 1) / 2, NOUT = 1 + P + P2;
-  constexpr int SH = H / 4, S1 = (P + 3) / 4;
+  constexpr int SH = H / 4, S1 = (P + 3) / 4, NPB = (P2 + 15) / 16;
   constexpr int CH = (L >= 3) ? 3 : 1;  // gradient columns per LDS exchange chunk
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
-  const int64_t base = (int64_t)blockIdx.x * 16;
-  const int64_t qp = base + q;
-  const bool valid = qp < n;
 
-  __shared__ T W1s[P][H];
+  __shared__ T W1s[P][H];          // W1^T
+  __shared__ T Bs[L - 1][P][H];    // B_k^T, k = 2..L
   __shared__ double outp[NW][NOUT][16];
   __shared__ T xbuf[CH][H][16];
   __shared__ T l1buf[2][H][16];
+  __shared__ T cs[L][H], as_[H];   // biases and output weights
 
   const bool dbl = std::is_same<T, double>::value;
   const T* t_W1t = (const T*)(prep + (dbl ? lay.d_W1t : lay.f_W1t));
@@ -594,36 +637,19 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   const T* t_c = (const T*)(prep + (dbl ? lay.d_c : lay.f_c));
   const T* t_Bt = (const T*)(prep + (dbl ? lay.d_Bt : lay.f_Bt));
   const double* d_b = (const double*)(prep + lay.d_b);
-  const typename E::frag* fW1 = frag_ptr<E>(prep, lay, 0);
-  const typename E::frag* fA = frag_ptr<E>(prep, lay, 1);
-  const typename E::frag* fB = frag_ptr<E>(prep, lay, 2);
-  const typename E::frag* fAT = (const typename E::frag*)(prep + (dbl ? lay.x_AT : lay.y_AT));
+  const frag_t* fW1 = frag_ptr<E>(prep, lay, 0);
+  const frag_t* fA = frag_ptr<E>(prep, lay, 1);
+  const frag_t* fB = frag_ptr<E>(prep, lay, 2);
+  const frag_t* fAT = (const frag_t*)(prep + (dbl ? lay.x_AT : lay.y_AT));
+  const frag_t* fG1 = (const frag_t*)(prep + (dbl ? lay.x_G1 : lay.y_G1));
 
+  // ---- once per workgroup: weight tables in LDS, this wave's fragments and
+  // per-row constants in registers (reused by every tile)
   for (int i = tid; i < P * H; i += 64 * NW) W1s[i / H][i % H] = t_W1t[i];
-  typename E::frag kB[S1];
+  for (int i = tid; i < (L - 1) * P * H; i += 64 * NW) (&Bs[0][0][0])[i] = t_Bt[(int64_t)P * H + i];
+  frag_t a1[S1], AV[L - 1][SH], BV[L - 1][S1];
 #pragma unroll
-  for (int s = 0; s < S1; ++s) {
-    const int m = 4 * s + g;
-    kB[s] = (valid && m < P) ? (T)Kin[(int64_t)m * n + qp] : (T)0;
-  }
-  // layer 1: own rows, then z_1 and F'(y_1) of every row through LDS
-  T t1w[4], z1[MB][4];
-  {
-    typename E::frag a1[S1];
-#pragma unroll
-    for (int s = 0; s < S1; ++s) a1[s] = fW1[(w * S1 + s) * 64 + lane];
-    acc_t acc = mma_in<E, P>(a1, kB, zero_acc<E>());
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      T f, f1, f2;
-      const int r = 16 * w + E::row(g, v);
-      softplus3((T)(acc[v] + t_c[r]), f, f1, f2);
-      t1w[v] = f2;
-      l1buf[0][r][q] = f;
-      l1buf[1][r][q] = f1;
-    }
-  }
-  typename E::frag AV[L - 1][SH], BV[L - 1][S1];
+  for (int s = 0; s < S1; ++s) a1[s] = fW1[(w * S1 + s) * 64 + lane];
 #pragma unroll
   for (int k = 2; k <= L; ++k) {
 #pragma unroll
@@ -631,197 +657,256 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 #pragma unroll
     for (int s = 0; s < S1; ++s) BV[k - 2][s] = fB[(((k - 1) * MB + w) * S1 + s) * 64 + lane];
   }
-  T a_own[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) a_own[v] = t_a[16 * w + E::row(g, v)];
-  __syncthreads();  // W1s, l1buf
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      z1[mb][v] = l1buf[0][16 * mb + E::row(g, v)][q];
-    }
+  for (int i = tid; i < L * H; i += 64 * NW) (&cs[0][0])[i] = t_c[i];
+  for (int i = tid; i < H; i += 64 * NW) as_[i] = t_a[i];
+  __syncthreads();  // W1s, Bs, cs, as_
 
-  // ---- 1. value forward (own rows of layers 2..L)
-  T sk[L - 1][4], tk[L - 1][4];
-  {
-    T src[MB][4];
+  const int64_t ntiles = (n + 15) / 16;
+  auto tile_body = [&](int64_t tile) {
+    const int64_t base = tile * 16;
+    const int64_t qp = base + q;
+    const bool valid = qp < n;
+    frag_t kB[S1];
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) src[mb][v] = z1[mb][v];
-    static_for<L - 1>([&](auto KI) {
-      constexpr int k = decltype(KI)::value + 2;
-      if constexpr (k >= 3) {
-        __syncthreads();
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) src[mb][v] = xbuf[0][16 * mb + E::row(g, v)][q];
-        __syncthreads();
-      }
-      acc_t acc = mma_in<E, P>(BV[k - 2], kB, mma_src<E, MB>(AV[k - 2], src, zero_acc<E>()));
-      T o[4];
+    for (int s = 0; s < S1; ++s) {
+      const int m = 4 * s + g;
+      kB[s] = (valid && m < P) ? (T)Kin[(int64_t)m * n + qp] : (T)0;
+    }
+    // layer 1: own rows, then z_1 and F'(y_1) of every row through LDS
+    T t1w[4], s1w[4], z1[MB][4];
+    {
+      acc_t acc = mma_in<E, P>(a1, kB, zero_acc<E>());
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         T f, f1, f2;
-        softplus3((T)(acc[v] + t_c[(k - 1) * H + 16 * w + E::row(g, v)]), f, f1, f2);
-        sk[k - 2][v] = f1; tk[k - 2][v] = f2; o[v] = f;
+        const int r = 16 * w + E::row(g, v);
+        softplus3((T)(acc[v] + cs[0][r]), f, f1, f2);
+        t1w[v] = f2;
+        s1w[v] = f1;
+        l1buf[0][r][q] = f;
+        l1buf[1][r][q] = f1;
       }
-      if constexpr (k < L) {
+    }
+    __syncthreads();  // l1buf
 #pragma unroll
-        for (int v = 0; v < 4; ++v) xbuf[0][16 * w + E::row(g, v)][q] = o[v];
-      } else {
-        double pl = 0.0;
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) pl += (double)(a_own[v] * o[v]);
-        pl = group_sum(pl);
-        if (g == 0) outp[w][0][q] = pl;
-      }
-    });
-  }
+      for (int v = 0; v < 4; ++v) z1[mb][v] = l1buf[0][16 * mb + E::row(g, v)][q];
 
-  // ---- 2. reverse sweep: gamma_k = lambda_k (.) F''(y_k), own rows
-  T gam[L][4];
-  if (hess) {
-    T lam[4], mu[4];
+    // ---- 1. value forward (own rows of layers 2..L)
+    T sk[L - 1][4], tk[L - 1][4];
+    {
+      T src[MB][4];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) src[mb][v] = z1[mb][v];
+      static_for<L - 1>([&](auto KI) {
+        constexpr int k = decltype(KI)::value + 2;
+        if constexpr (k >= 3) {
+          __syncthreads();
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) src[mb][v] = xbuf[0][16 * mb + E::row(g, v)][q];
+          __syncthreads();
+        }
+        acc_t acc = mma_in<E, P>(BV[k - 2], kB, mma_src<E, MB>(AV[k - 2], src, zero_acc<E>()));
+        T o[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          T f, f1, f2;
+          softplus3((T)(acc[v] + cs[k - 1][16 * w + E::row(g, v)]), f, f1, f2);
+          sk[k - 2][v] = f1; tk[k - 2][v] = f2; o[v] = f;
+        }
+        if constexpr (k < L) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) xbuf[0][16 * w + E::row(g, v)][q] = o[v];
+        } else {
+          double pl = 0.0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) pl += (double)(as_[16 * w + E::row(g, v)] * o[v]);
+          pl = group_sum(pl);
+          if (g == 0) outp[w][0][q] = pl;
+        }
+      });
+    }
+
+    // ---- 2. reverse sweep: mu_k = lambda_k (.) F'(y_k) and
+    // gamma_k = lambda_k (.) F''(y_k), own rows
+    T mus[L][4], gam[L][4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      lam[v] = a_own[v];
-      gam[L - 1][v] = lam[v] * tk[L - 2][v];
-      mu[v] = lam[v] * sk[L - 2][v];
+      const T a = as_[16 * w + E::row(g, v)];
+      gam[L - 1][v] = a * tk[L - 2][v];
+      mus[L - 1][v] = a * sk[L - 2][v];
     }
     static_for<L - 1>([&](auto KI) {
       constexpr int k = L - decltype(KI)::value;  // L .. 2: lambda_{k-1} = A_k^T mu_k
       __syncthreads();
 #pragma unroll
-      for (int v = 0; v < 4; ++v) xbuf[0][16 * w + E::row(g, v)][q] = mu[v];
+      for (int v = 0; v < 4; ++v) xbuf[0][16 * w + E::row(g, v)][q] = mus[k - 1][v];
       __syncthreads();
-      const typename E::frag* at = fAT + (((k - 1) * MB + w) * SH) * 64 + lane;
+      const frag_t* at = fAT + (((k - 1) * MB + w) * SH) * 64 + lane;
       acc_t acc = zero_acc<E>();
 #pragma unroll
-      for (int s = 0; s < SH; ++s) acc = E::mma(at[s * 64], (typename E::frag)xbuf[0][4 * s + g][q], acc);
+      for (int s = 0; s < SH; ++s) acc = E::mma(at[s * 64], (frag_t)xbuf[0][4 * s + g][q], acc);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const T l = (T)acc[v];
         if constexpr (k - 1 >= 2) {
           gam[k - 2][v] = l * tk[k - 3][v];
-          mu[v] = l * sk[k - 3][v];
+          mus[k - 2][v] = l * sk[k - 3][v];
         } else {
           gam[0][v] = l * t1w[v];
+          mus[0][v] = l * s1w[v];
         }
       }
     });
-    __syncthreads();  // xbuf free
-  }
 
-  // ---- 3. Jacobian forward with the Gram sums.  Each layer's sum over the
-  // wave's 16 rows is reduced four pairs at a time (reduce4) and added into
-  // outp, so no per-lane Hessian partials stay live across layers.
-  // gram(layer, col): adds sum_rows gamma_layer * col(m) * col(n) for every pair.
-  auto gram = [&](const T (&gm)[4], auto colv, bool first) {
-    static_for<(P2 + 3) / 4>([&](auto BI) {
+    // ---- 3. gradient: dN/dK_m = b_m + sum_rows mu_1 W1[., m] + sum_k mu_k B_k[., m]
+    static_for<(P + 3) / 4>([&](auto BI) {
       constexpr int c0 = decltype(BI)::value * 4;
-      double pp[4];
+      double gp[4];
       static_for<4>([&](auto JI) {
         constexpr int j = decltype(JI)::value;
-        constexpr int h = (c0 + j < P2) ? c0 + j : 0;
-        constexpr int m = hess_m(h, P), nn = hess_n(h, P);
         T x = (T)0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) x += gm[v] * colv(m, v) * colv(nn, v);
-        pp[j] = (c0 + j < P2) ? (double)x : 0.0;
-      });
-      const double r = reduce4(pp[0], pp[1], pp[2], pp[3], g);
-      if (c0 + g < P2) {
-        double& o = outp[w][1 + P + c0 + g][q];
-        o = first ? r : o + r;
-      }
-    });
-  };
-  if (hess) {  // layer 1: J_1 = W1 (own rows of block w)
-    gram(gam[0], [&](int m, int v) { return W1s[m][16 * w + E::row(g, v)]; }, true);
-  }
-  T J[P][4];  // dy_k/dK_m, own rows of the current layer
-  static_for<L - 1>([&](auto KI) {
-    constexpr int k = decltype(KI)::value + 2;
-    if constexpr (k == 2) {
-      static_for<P>([&](auto MI) {
-        constexpr int m = decltype(MI)::value;
-        T src[MB][4];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+        if constexpr (c0 + j < P) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int r = 16 * mb + E::row(g, v);
-            src[mb][v] = l1buf[1][r][q] * W1s[m][r];
-          }
-        acc_t acc = mma_src<E, MB>(AV[0], src, zero_acc<E>());
+            const int r = 16 * w + E::row(g, v);
+            x += mus[0][v] * W1s[c0 + j][r];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) J[m][v] = (T)acc[v] + t_Bt[((int64_t)1 * P + m) * H + 16 * w + E::row(g, v)];
+            for (int k = 2; k <= L; ++k) x += mus[k - 1][v] * Bs[k - 2][c0 + j][r];
+          }
+        }
+        gp[j] = (double)x;
       });
-    } else {
-      // exchange dz_{k-1}/dK_m = F'(y_{k-1}) J_{k-1} in chunks of CH columns
-      static_for<(P + CH - 1) / CH>([&](auto CI) {
-        constexpr int c0 = decltype(CI)::value * CH;
-        __syncthreads();
-        static_for<CH>([&](auto JI) {
-          constexpr int m = c0 + decltype(JI)::value;
-          if constexpr (m < P) {
+      const double r = reduce4(gp[0], gp[1], gp[2], gp[3], g);
+      if (c0 + g < P) outp[w][1 + c0 + g][q] = r;
+    });
+
+    if constexpr (HESS) {
+      // ---- 4. layer-1 Gram on the matrix cores: rows of this wave's block,
+      // B operand of K step s = gamma_1 at row(g, s) (already in registers)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) xbuf[m - c0][16 * w + E::row(g, v)][q] = sk[k - 3][v] * J[m][v];
-          }
-        });
-        __syncthreads();
-        static_for<CH>([&](auto JI) {
-          constexpr int m = c0 + decltype(JI)::value;
-          if constexpr (m < P) {
+      for (int pb = 0; pb < NPB; ++pb) {
+        acc_t acc = zero_acc<E>();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = E::mma(fG1[((pb * MB + w) * 4 + s) * 64 + lane], (frag_t)gam[0][s], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int pr = 16 * pb + E::row(g, v);
+          if (pr < P2) outp[w][1 + P + pr][q] = (double)acc[v];  // table rows are packed pair indices
+        }
+      }
+
+      // ---- 5. Jacobian forward; Gram pairs of layer k summed as columns form
+      T J[P][4];  // dy_k/dK_m, own rows of the current layer
+      double pp[4];
+      // pair t (column-major) of layer k: sum over the wave's rows, flushed
+      // every four pairs into outp at the packed positions of those pairs
+      auto pair_sum = [&](auto TI, const T (&gm)[4]) {
+        constexpr int t = decltype(TI)::value;
+        constexpr int m = colmaj_m(t), nn = colmaj_n(t);
+        T x = (T)0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x += gm[v] * J[nn][v] * J[m][v];
+        pp[t % 4] = (double)x;
+        if constexpr (t % 4 == 3 || t == P2 - 1) {
+          constexpr int c0 = t - t % 4;
+#pragma unroll
+          for (int j = t % 4 + 1; j < 4; ++j) pp[j] = 0.0;
+          const double r = reduce4(pp[0], pp[1], pp[2], pp[3], g);
+          constexpr int h0 = packed_index(colmaj_n(c0), colmaj_m(c0), P);
+          constexpr int h1 = (c0 + 1 < P2) ? packed_index(colmaj_n(c0 + 1), colmaj_m(c0 + 1), P) : 0;
+          constexpr int h2 = (c0 + 2 < P2) ? packed_index(colmaj_n(c0 + 2), colmaj_m(c0 + 2), P) : 0;
+          constexpr int h3 = (c0 + 3 < P2) ? packed_index(colmaj_n(c0 + 3), colmaj_m(c0 + 3), P) : 0;
+          const int h = g == 0 ? h0 : g == 1 ? h1 : g == 2 ? h2 : h3;
+          if (c0 + g < P2) outp[w][1 + P + h][q] += r;
+        }
+      };
+      static_for<L - 1>([&](auto KI) {
+        constexpr int k = decltype(KI)::value + 2;
+        if constexpr (k == 2) {
+          static_for<P>([&](auto MI) {
+            constexpr int m = decltype(MI)::value;
             T src[MB][4];
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-              for (int v = 0; v < 4; ++v) src[mb][v] = xbuf[m - c0][16 * mb + E::row(g, v)][q];
-            acc_t acc = mma_src<E, MB>(AV[k - 2], src, zero_acc<E>());
+              for (int v = 0; v < 4; ++v) {
+                const int r = 16 * mb + E::row(g, v);
+                src[mb][v] = l1buf[1][r][q] * W1s[m][r];
+              }
+            acc_t acc = mma_src<E, MB>(AV[0], src, zero_acc<E>());
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-              J[m][v] = (T)acc[v] + t_Bt[((int64_t)(k - 1) * P + m) * H + 16 * w + E::row(g, v)];
-          }
-        });
+            for (int v = 0; v < 4; ++v) J[m][v] = (T)acc[v] + Bs[0][m][16 * w + E::row(g, v)];
+            static_for<m + 1>([&](auto NI) {
+              pair_sum(std::integral_constant<int, m * (m + 1) / 2 + decltype(NI)::value>{}, gam[1]);
+            });
+          });
+        } else {
+          // exchange dz_{k-1}/dK_m = F'(y_{k-1}) J_{k-1} in chunks of CH columns
+          static_for<(P + CH - 1) / CH>([&](auto CI) {
+            constexpr int c0 = decltype(CI)::value * CH;
+            __syncthreads();
+            static_for<CH>([&](auto JI) {
+              constexpr int m = c0 + decltype(JI)::value;
+              if constexpr (m < P) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) xbuf[m - c0][16 * w + E::row(g, v)][q] = sk[k - 3][v] * J[m][v];
+              }
+            });
+            __syncthreads();
+            static_for<CH>([&](auto JI) {
+              constexpr int m = c0 + decltype(JI)::value;
+              if constexpr (m < P) {
+                T src[MB][4];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                  for (int v = 0; v < 4; ++v) src[mb][v] = xbuf[m - c0][16 * mb + E::row(g, v)][q];
+                acc_t acc = mma_src<E, MB>(AV[k - 2], src, zero_acc<E>());
+#pragma unroll
+                for (int v = 0; v < 4; ++v) J[m][v] = (T)acc[v] + Bs[k - 2][m][16 * w + E::row(g, v)];
+              }
+            });
+            // Gram pairs of the columns just formed (their partners n <= m are ready)
+            static_for<CH>([&](auto JI) {
+              constexpr int m = c0 + decltype(JI)::value;
+              if constexpr (m < P)
+                static_for<m + 1>([&](auto NI) {
+                  pair_sum(std::integral_constant<int, m * (m + 1) / 2 + decltype(NI)::value>{}, gam[k - 1]);
+                });
+            });
+          });
+        }
       });
     }
-    if (hess) gram(gam[k - 1], [&](int m, int v) { return J[m][v]; }, false);
-  });
-  // gradient outputs: dN/dK_m = sum_j a_j F'(y_L,j) J_L[j, m] (+ b_m below)
-  static_for<(P + 3) / 4>([&](auto BI) {
-    constexpr int c0 = decltype(BI)::value * 4;
-    double pp[4];
+
+    __syncthreads();  // outp complete
+    constexpr int nout_written = HESS ? NOUT : 1 + P;
+    for (int i = tid; i < nout_written * 16; i += 64 * NW) {
+      const int c = i / 16, qq = i % 16;
+      const int64_t pt = base + qq;
+      if (pt >= n) continue;
+      double v = 0.0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      double x = 0.0;
-      if (c0 + j < P) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) x += (double)(a_own[v] * sk[L - 2][v] * J[c0 + j < P ? c0 + j : 0][v]);
+      for (int ww = 0; ww < NW; ++ww) v += outp[ww][c][qq];
+      if (c == 0) {
+        for (int m = 0; m < P; ++m) v += d_b[m] * Kin[(int64_t)m * n + pt];
+      } else if (c <= P) {
+        v += d_b[c - 1];
       }
-      pp[j] = x;
+      out[(int64_t)c * n + pt] = v;
     }
-    const double r = reduce4(pp[0], pp[1], pp[2], pp[3], g);
-    if (c0 + g < P) outp[w][1 + c0 + g][q] = r;
-  });
-  __syncthreads();
-  const int nout_written = hess ? NOUT : 1 + P;
-  for (int i = tid; i < nout_written * 16; i += 64 * NW) {
-    const int c = i / 16, qq = i % 16;
-    const int64_t pt = base + qq;
-    if (pt >= n) continue;
-    double v = 0.0;
-#pragma unroll
-    for (int ww = 0; ww < NW; ++ww) v += outp[ww][c][qq];
-    if (c == 0) {
-      for (int m = 0; m < P; ++m) v += d_b[m] * Kin[(int64_t)m * n + pt];
-    } else if (c <= P) {
-      v += d_b[c - 1];
-    }
-    out[(int64_t)c * n + pt] = v;
+    __syncthreads();  // outp, l1buf and xbuf free for the next tile
+  };
+  if constexpr (HESS) {
+    tile_body(blockIdx.x);  // one tile per workgroup (see the launcher)
+  } else {
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) tile_body(tile);
   }
 }
 
@@ -853,14 +938,49 @@ bool mlp_supported(int H, int L, int P) {
   return false;
 }
 
+// Persistent launch: as many workgroups as fit on the device at once (so the
+// per-workgroup set-up is paid once per resident group), never more than the
+// number of 16-point tiles.
+template <class K>
+static unsigned persistent_grid(K kernel, int block, int64_t ntiles) {
+  static thread_local int cached_dev = -1, cached_cap = 0;
+  static thread_local const void* cached_k = nullptr;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (cached_k != (const void*)kernel || cached_dev != dev) {
+    int cus = 0, per_cu = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
+    cached_cap = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
+    cached_k = (const void*)kernel;
+    cached_dev = dev;
+  }
+  return (unsigned)(ntiles < cached_cap ? ntiles : cached_cap);
+}
+
+template <int H, int L, int P, int PR, bool HESS>
+static void launch_adj_one(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
+                           double* out, hipStream_t s) {
+  const int block = 64 * (H / 16);
+  // with the Hessian the per-tile state leaves no registers for keeping the
+  // weight fragments across tiles: one tile per workgroup
+  const int64_t ntiles = (n + 15) / 16;
+  const unsigned grid = HESS ? (unsigned)ntiles : persistent_grid(k_mlp_adj<H, L, P, PR, HESS>, block, ntiles);
+  k_mlp_adj<H, L, P, PR, HESS><<<grid, block, 0, s>>>(prep, lay, n, K, out);
+}
+
 template <int H, int L, int P>
 static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char* prep, int64_t n,
                             const double* K, double* out, int hess, hipStream_t s) {
-  const unsigned grid = (unsigned)((n + 15) / 16);
-  const unsigned block = 64 * (H / 16);
   switch (prec) {
-    case PREC_F64: k_mlp_adj<H, L, P, PREC_F64><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
-    case PREC_F32: k_mlp_adj<H, L, P, PREC_F32><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
+    case PREC_F64:
+      if (hess) launch_adj_one<H, L, P, PREC_F64, true>(lay, prep, n, K, out, s);
+      else launch_adj_one<H, L, P, PREC_F64, false>(lay, prep, n, K, out, s);
+      break;
+    case PREC_F32:
+      if (hess) launch_adj_one<H, L, P, PREC_F32, true>(lay, prep, n, K, out, s);
+      else launch_adj_one<H, L, P, PREC_F32, false>(lay, prep, n, K, out, s);
+      break;
     default: return -2;
   }
   return 0;
