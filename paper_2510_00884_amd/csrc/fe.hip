@@ -128,22 +128,24 @@ __global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, const int32_t* _
 }
 
 // ---------------------------------------------------------------- chain rule + integration
-// Element kernel over a block of E = 8 elements, one thread per element row
-// rho = 3a + i (E * 3 nen threads):
-//  phase A: F, S~ = dPsi/dC, CC~ = d2Psi/dCdC (tensor components, formed per
-//    point by the material kernel) and w of the block's E * nq points into
-//    LDS, coalesced (point index q * n_el + e);
-//  phase B: for every point q, with the shape gradients of q staged in LDS
-//    (the next point's are fetched while q is computed, double buffered):
-//    r^a_i      += w 2 (F S~ G^a)_i,                     G^a = dN^a/dX
-//    K^ab_ik    += w [2 delta_ik G^a.S~ G^b + 4 F_iI F_kK G^a_J CC~_IJKL G^b_L]
-//  i.e. the material form  sum_q w G^a_J AA_iJkL G^b_L  with AA never stored.
-// MODE 0 (tables) writes r_e [nd][n_el] and K_e [nd][nd][n_el] (threads
-// element-fastest for coalesced stores); MODE 1 (scatter) adds the rows
-// straight into the global r and CSR values (one launch per colour, so no
-// two threads touch the same entry); MODE 2 (element-major tables) writes
-// r_e [n_el][nd] and K_e [n_el][nd][nd], the layout read by the gather
-// assembly.  MODE 1 and 2 order threads row-fastest.
+// Element kernel over a block of E = 8 elements, 3 nen threads per element:
+//  phase A (one thread per point q and row i of its tangent): from F,
+//    S~ = dPsi/dC and CC~ = d2Psi/dCdC (tensor components per point, from
+//    the material kernel) forms, scaled by the quadrature weight w,
+//      P_iJ       = 2 F_iI S~_IJ
+//      AA_iJkL    = 2 delta_ik S~_JL + 4 F_iI F_kK CC~_IJKL      (27 per row)
+//    into LDS;
+//  phase B (one thread per element row rho = 3a + i, row index i uniform
+//    across a wave; the block's shape gradients of every point are staged in
+//    LDS during phase A, so the loop over points has no barrier):
+//      r^a_i   += w P_iJ G^a_J
+//      K^ab_ik += (w AA_iJkL G^a_J) G^b_L,                G^a = dN^a/dX
+//    the material form of eqs. k-quad and r-quad.
+// MODE 0 (tables) writes r_e [nd][n_el] and K_e [nd][nd][n_el]; MODE 1
+// (scatter) adds the rows straight into the global r and CSR values (one
+// launch per colour, so no two threads touch the same entry); MODE 2
+// (element-major tables) writes r_e [n_el][nd] and K_e [n_el][nd][nd], the
+// layout read by the gather assembly.
 template <int NEN>
 __host__ __device__ constexpr int integrate_threads() { return 8 * 3 * NEN; }
 
@@ -158,54 +160,80 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
   constexpr int ND = 3 * NEN;
   constexpr int E = 8;
   constexpr int NT = integrate_threads<NEN>();
-  constexpr int NPT = E * NQ;  // points per block
+  constexpr int NPT = E * NQ;      // points per block
   constexpr int NG = E * NEN * 3;  // shape-gradient values per point slice
   static_assert(NG == NT, "one shape-gradient value per thread per point");
-  __shared__ double sF[9][NPT], sS[6][NPT], sC[21][NPT], sW[NPT];
-  __shared__ double sG[2][NEN][3][E];
+  static_assert(3 * NPT <= NT, "one (point, row) pair per thread in phase A");
+  __shared__ double sA[3][3][9][NPT];  // w AA_iJ(kL)
+  __shared__ double sP[3][3][NPT];     // w P_iJ
+  __shared__ double sG[NQ][NEN][3][E];
   const int tid = threadIdx.x;
   const int64_t eb = e_begin + (int64_t)blockIdx.x * E;
   const int64_t e_end = e_begin + e_count;
   const int64_t n = n_el * NQ;
-  // phase A: every thread loads a share of the (component, point) pairs, so
-  // the block's loads are all in flight at once; point t = q * E + le
-  {
-    constexpr int NLD = (37 * NPT + NT - 1) / NT;
-    double v[NLD];
-#pragma unroll
-    for (int k = 0; k < NLD; ++k) {  // all loads issued before any is used
-      const int idx = tid + k * NT;
-      const int c = idx / NPT, t = idx % NPT;
-      const int64_t e = eb + t % E;
-      const int64_t pt = (int64_t)(t / E) * n_el + e;
-      v[k] = 0.0;
-      if (idx < 37 * NPT && e < e_end)
-        v[k] = (c < 9) ? F[(int64_t)c * n + pt] : (c < 36) ? SC[(int64_t)(c - 9) * n + pt] : w[pt];
-    }
-#pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-      const int idx = tid + k * NT;
-      if (idx >= 37 * NPT) break;
-      const int c = idx / NPT, t = idx % NPT;
-      if (c < 9) sF[c][t] = v[k];
-      else if (c < 15) sS[c - 9][t] = v[k];
-      else if (c < 36) sC[c - 15][t] = v[k];
-      else sW[t] = v[k];
-    }
-  }
+
   // this thread's shape-gradient value of every point slice: (b, J, le)
   const int g_le = tid % E, g_J = (tid / E) % 3, g_b = tid / (3 * E);
   const int64_t g_e = eb + g_le;
-  auto load_g = [&](int q) -> double {
-    return (g_e < e_end) ? dNdX[(((int64_t)q * NEN + g_b) * 3 + g_J) * n_el + g_e] : 0.0;
-  };
-  sG[0][g_b][g_J][g_le] = load_g(0);
+  double gv[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    gv[q] = (g_e < e_end) ? dNdX[(((int64_t)q * NEN + g_b) * 3 + g_J) * n_el + g_e] : 0.0;
+
+  // phase A: (point t = q * E + le, row i)
+  if (tid < 3 * NPT) {
+    const int i = tid % 3, t = tid / 3;
+    const int le = t % E, q = t / E;
+    const int64_t e = eb + le;
+    double Fm[9], S[6], Cc[21], wq = 0.0;
+    if (e < e_end) {
+      const int64_t pt = (int64_t)q * n_el + e;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) Fm[c] = F[(int64_t)c * n + pt];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) S[c] = SC[(int64_t)c * n + pt];
+#pragma unroll
+      for (int c = 0; c < 21; ++c) Cc[c] = SC[(int64_t)(6 + c) * n + pt];
+      wq = w[pt];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) Fm[c] = 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) S[c] = 0.0;
+#pragma unroll
+      for (int c = 0; c < 21; ++c) Cc[c] = 0.0;
+    }
+    double Fi[3];  // row i of F
+#pragma unroll
+    for (int I = 0; I < 3; ++I) Fi[I] = (i == 0) ? Fm[I] : (i == 1) ? Fm[3 + I] : Fm[6 + I];
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      sP[i][J][t] = wq * 2.0 * (Fi[0] * S[VI(0, J)] + Fi[1] * S[VI(1, J)] + Fi[2] * S[VI(2, J)]);
+      // Y_KL = sum_I F_iI CC~_IJKL
+      double Y[3][3];
+#pragma unroll
+      for (int K = 0; K < 3; ++K)
+#pragma unroll
+        for (int L = 0; L < 3; ++L)
+          Y[K][L] = Fi[0] * Cc[TRI(VI(0, J), VI(K, L))] + Fi[1] * Cc[TRI(VI(1, J), VI(K, L))] +
+                    Fi[2] * Cc[TRI(VI(2, J), VI(K, L))];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int L = 0; L < 3; ++L) {
+          double v = 4.0 * (Fm[3 * k] * Y[0][L] + Fm[3 * k + 1] * Y[1][L] + Fm[3 * k + 2] * Y[2][L]);
+          if (k == i) v += 2.0 * S[VI(J, L)];
+          sA[i][J][3 * k + L][t] = wq * v;
+        }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) sG[q][g_b][g_J][g_le] = gv[q];
   __syncthreads();
 
-  // phase B: (element le, row rho = 3a + i)
-  const int le = (MODE == 0) ? tid % E : tid / ND;
-  const int rho = (MODE == 0) ? tid / E : tid % ND;
-  const int a = rho / 3, i = rho % 3;
+  // phase B: thread (row i, node a, element le), i outermost
+  const int le = tid % E, a = (tid / E) % NEN, i = tid / (E * NEN);
+  const int rho = 3 * a + i;
   const int64_t e = eb + le;
   double acc[ND];
 #pragma unroll
@@ -213,54 +241,21 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
   double rr = 0.0;
 #pragma unroll 1
   for (int q = 0; q < NQ; ++q) {
-    const int buf = q & 1;
-    const double gnext = (q + 1 < NQ) ? load_g(q + 1) : 0.0;  // in flight during this point
+    const int buf = q;
     const int lq = q * E + le;
     double ga[3];
 #pragma unroll
     for (int J = 0; J < 3; ++J) ga[J] = sG[buf][a][J][le];
-    const double wq = sW[lq];
-    double Fi[3];  // row i of F
+    rr += sP[i][0][lq] * ga[0] + sP[i][1][lq] * ga[1] + sP[i][2][lq] * ga[2];
+    double T[9];  // T_kL = w AA_iJkL G^a_J
 #pragma unroll
-    for (int I = 0; I < 3; ++I) Fi[I] = sF[3 * i + I][lq];
-    double Sg[3];  // S~ G^a
-#pragma unroll
-    for (int I = 0; I < 3; ++I) Sg[I] = sS[VI(I, 0)][lq] * ga[0] + sS[VI(I, 1)][lq] * ga[1] + sS[VI(I, 2)][lq] * ga[2];
-    rr += wq * 2.0 * (Fi[0] * Sg[0] + Fi[1] * Sg[1] + Fi[2] * Sg[2]);
-    // Wv_KL = sum_I F_iI sum_J G^a_J CC~_IJKL   (row i only)
-    double Wv[3][3];
-#pragma unroll
-    for (int K = 0; K < 3; ++K)
-#pragma unroll
-      for (int L = 0; L < 3; ++L) {
-        double s = 0.0;
-#pragma unroll
-        for (int I = 0; I < 3; ++I) {
-          double v = 0.0;
-#pragma unroll
-          for (int J = 0; J < 3; ++J) v += ga[J] * sC[TRI(VI(I, J), VI(K, L))][lq];
-          s += Fi[I] * v;
-        }
-        Wv[K][L] = s;
-      }
-    // T_kL = 4 sum_K F_kK Wv_KL + 2 delta_ik (S~ G^a)_L, scaled by w
-    double T[3][3];
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-      for (int L = 0; L < 3; ++L) {
-        double s = sF[3 * kk][lq] * Wv[0][L] + sF[3 * kk + 1][lq] * Wv[1][L] + sF[3 * kk + 2][lq] * Wv[2][L];
-        s = 4.0 * s + (kk == i ? 2.0 * Sg[L] : 0.0);
-        T[kk][L] = wq * s;
-      }
+    for (int c = 0; c < 9; ++c) T[c] = sA[i][0][c][lq] * ga[0] + sA[i][1][c][lq] * ga[1] + sA[i][2][c][lq] * ga[2];
 #pragma unroll
     for (int b = 0; b < NEN; ++b) {
-      const double g0 = sG[buf][b][0][le], g1 = sG[buf][b][1][le], g2 = sG[buf][b][2][le];
+      const double h0 = sG[buf][b][0][le], h1 = sG[buf][b][1][le], h2 = sG[buf][b][2][le];
 #pragma unroll
-      for (int kk = 0; kk < 3; ++kk) acc[3 * b + kk] += T[kk][0] * g0 + T[kk][1] * g1 + T[kk][2] * g2;
+      for (int kk = 0; kk < 3; ++kk) acc[3 * b + kk] += T[3 * kk] * h0 + T[3 * kk + 1] * h1 + T[3 * kk + 2] * h2;
     }
-    if (q + 1 < NQ) sG[buf ^ 1][g_b][g_J][g_le] = gnext;
-    __syncthreads();
   }
   if (e >= e_end) return;
   if constexpr (MODE == 0) {
