@@ -30,6 +30,27 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "bf16_corr": 2.5e15}
 HBM_PEAK = 8.0e12
 
 
+def measured_traffic(kernel_symbol):
+    """HBM bytes per launch of a kernel from the committed FETCH_SIZE /
+    WRITE_SIZE summary (profiles/traffic.json), or None when that summary is
+    for another kernel or the kernel's sources have changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tr = json.load(fh)
+    if tr.get("symbol") != kernel_symbol:
+        return None
+    h = hashlib.sha256()
+    for src in tr["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != tr["sources_sha256"]:
+        return None
+    return tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+
+
 def mlp_flops_per_point(h, L, p):
     """Alg. 4 forward mode: 2h^2 c (L-1) + 2hc + 2hpL + 4h P2 (L-1) + h P2,
     c = 1 + p + P2 columns, P2 = p(p+1)/2."""
@@ -223,8 +244,10 @@ def main():
         if dom.startswith("mlp"):
             fl = mlp_flops(dom, h, Lh, p) * n_qp
             ach = fl / per_launch_s
+            sym = "k_mlp_adj<{}, {}, {}, {}, true>".format(h, Lh, p, {"fp64": 0, "fp32": 1}.get(args.prec, -1)) \
+                if dom == "mlp_adjoint" else None
             roof = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[args.prec] / 1e12, "unit": "TFLOP/s",
-                    "frac": ach / PEAK[args.prec], "traffic": None, "kernel": dom,
+                    "frac": ach / PEAK[args.prec], "traffic": measured_traffic(sym) if sym else None, "kernel": dom,
                     "algorithmic_per_launch": f"{mlp_flops(dom, h, Lh, p)} FLOP/point x {n_qp} points"}
         else:
             launches_per_step = kern[dom]["launches"] / args.steps
