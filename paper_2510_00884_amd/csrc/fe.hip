@@ -7,6 +7,16 @@ namespace pa {
 
 static inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
+// XCD b mod 8), and each XCD has its own L2.  This bijection on [0, G) gives
+// every XCD a contiguous run of logical blocks, so neighbouring blocks (which
+// share cache lines at their element boundaries) share an L2.
+__device__ inline int64_t xcd_swizzle(int64_t b, int64_t G) {
+  constexpr int64_t X = 8;
+  const int64_t x = b % X, j = b / X, q = G / X, r = G % X;
+  return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
 // ---------------------------------------------------------------- shapes
 // Reference-coordinate derivatives dN_a/dxi_d at quadrature point q.
 template <int NEN>
@@ -168,7 +178,7 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
   __shared__ double sP[3][3][NPT];     // w P_iJ
   __shared__ double sG[NQ][NEN][3][E];
   const int tid = threadIdx.x;
-  const int64_t eb = e_begin + (int64_t)blockIdx.x * E;
+  const int64_t eb = e_begin + xcd_swizzle(blockIdx.x, gridDim.x) * E;
   const int64_t e_end = e_begin + e_count;
   const int64_t n = n_el * NQ;
 
