@@ -90,9 +90,9 @@ __global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restri
   if (!Pout && !Aout) return;
   const bool second = Aout != nullptr;
   auto N1 = [&](int m) { return Nout[(int64_t)(1 + m) * n + t]; };
-  auto N2 = [&](int i) { return second ? Nout[(int64_t)(1 + P + i) * n + t] : 0.0; };
+  auto N2 = [&](int i) { return Nout[(int64_t)(1 + P + i) * n + t]; };
   double S[6], CCt[21];
-  chain_material_lean<NSV>(k, mc, N1, N2, S, CCt);
+  chain_material_stream<NSV>(k, mc, N1, N2, second, S, CCt);
   push_material(
       k, S, CCt,
       [&](int c, double v) { if (Pout) Pout[(int64_t)c * n + t] = v; },
@@ -105,11 +105,10 @@ __global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restri
 // integrate.  Fully unrolled: the network derivatives are loaded once and the
 // feature gradients stay in registers.
 template <int NSV>
-__global__ void __launch_bounds__(256) k_material_cc(int64_t n, const double* __restrict__ F,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_material_cc(int64_t n, const double* __restrict__ F,
                                                      const double* __restrict__ Nout, ModelConst mc,
                                                      double* __restrict__ SC) {
   constexpr int P = Feat<NSV>::P;
-  constexpr int P2 = P * (P + 1) / 2;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   double f[9];
@@ -117,13 +116,10 @@ __global__ void __launch_bounds__(256) k_material_cc(int64_t n, const double* __
   for (int i = 0; i < 9; ++i) f[i] = F[i * n + t];
   Kin k;
   kin_compute<NSV>(f, mc, k);
-  double dN[P], d2N[P2];
-#pragma unroll
-  for (int m = 0; m < P; ++m) dN[m] = Nout[(int64_t)(1 + m) * n + t];
-#pragma unroll
-  for (int m = 0; m < P2; ++m) d2N[m] = Nout[(int64_t)(1 + P + m) * n + t];
+  auto N1 = [&](int m) { return Nout[(int64_t)(1 + m) * n + t]; };
+  auto N2 = [&](int i) { return Nout[(int64_t)(1 + P + i) * n + t]; };
   double S[6], CCt[21];
-  chain_material<NSV>(k, mc, dN, d2N, S, CCt);
+  chain_material_stream<NSV>(k, mc, N1, N2, true, S, CCt);
 #pragma unroll
   for (int c = 0; c < 6; ++c) SC[(int64_t)c * n + t] = S[c];
 #pragma unroll

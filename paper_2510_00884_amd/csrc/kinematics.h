@@ -368,6 +368,58 @@ __host__ __device__ inline void chain_material_lean(const Kin& k, const ModelCon
   chain_first_order<NSV>(k, mc, dN, CCt);
 }
 
+// Same result as chain_material with short live ranges, for kernels that
+// stream the network outputs from memory: the first-derivative terms are
+// applied while the kinematic quantities are live, then the feature
+// gradients D_m and S~, then the Gram part sum_m D_m (x) V_m with
+// V_m = sum_n N_mn D_n, reading the network Hessian one row at a time (an
+// empty compiler barrier keeps each row's loads from being hoisted above the
+// previous row's arithmetic).  N1(m) = dN/dK_m, N2(idx) = packed d2N;
+// second = false computes S~ only.
+template <int NSV, class G1, class G2>
+__host__ __device__ inline void chain_material_stream(const Kin& k, const ModelConst& mc, G1 N1, G2 N2,
+                                                      bool second, double* S, double* CCt) {
+  constexpr int P = Feat<NSV>::P;
+  double dN[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) dN[m] = N1(m);
+#pragma unroll
+  for (int t = 0; t < 21; ++t) CCt[t] = 0.0;
+  if (second) chain_first_order<NSV>(k, mc, dN, CCt);
+  double D[P][6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) S[a] = 0.0;
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    kin_dfeature<NSV>(k, mc, m, D[m]);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) S[a] += dN[m] * D[m][a];
+  }
+  if (!second) return;
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    asm volatile("" ::: "memory");
+    double wr[P];
+#pragma unroll
+    for (int n2 = 0; n2 < P; ++n2) {
+      const int mm = m < n2 ? m : n2, nn = m < n2 ? n2 : m;
+      wr[n2] = N2(mm * P - mm * (mm - 1) / 2 + (nn - mm));
+    }
+    double V[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double v = 0.0;
+#pragma unroll
+      for (int n2 = 0; n2 < P; ++n2) v += wr[n2] * D[n2][a];
+      V[a] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = a; b < 6; ++b) CCt[TRI(a, b)] += D[m][a] * V[b];
+  }
+}
+
 // P = 2 F S~ and AA_iJkL = 2 delta_ik S~_JL + 4 F_iI F_kK CC~_IJKL.
 // Calls sink(index, value) for the 9 stress and 81 tangent components.
 template <class StoreP, class StoreA>
