@@ -68,6 +68,8 @@ PrepLayout prep_layout(int H, int L, int P) {
     l.x_G1 = take(8 * (int64_t)npb * l.MB * 4 * 64);
     l.y_G1 = take(4 * (int64_t)npb * l.MB * 4 * 64);
   }
+  l.x_ATp = take(8 * (int64_t)L * l.MB * l.SH * 64);
+  l.y_ATp = take(4 * (int64_t)L * l.MB * l.SH * 64);
   l.k0 = take(8 * (int64_t)P * 16);
   l.nout = take(8 * (int64_t)l.NOUT * 16);
   l.total = o;
@@ -174,11 +176,27 @@ __global__ void k_prep_frags(const double* __restrict__ th, ThetaLayout t, PrepL
   const int64_t nG1 = (int64_t)NPB * MB * 4 * 64;
   double* xG1 = (double*)(prep + l.x_G1);
   float* yG1 = (float*)(prep + l.y_G1);
-  const int64_t total = nW1 + nA + nB + nzW1 + nzA + nzB + nAT + nG1;
+  const int64_t nATp = (int64_t)L * MB * SH * 64;
+  double* xATp = (double*)(prep + l.x_ATp);
+  float* yATp = (float*)(prep + l.y_ATp);
+  const int64_t total = nW1 + nA + nB + nzW1 + nzA + nzB + nAT + nG1 + nATp;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = idx;
-    if (j >= total - nG1) {  // [pb][w][s][lane]: W1_rm W1_rn, pair 16 pb + i, row 16w + row(g, s)
-      j -= total - nG1;
+    if (j >= total - nATp) {  // [k-1][mb][s = 4 ob + v][lane]: A_k[16 ob + row(g, v)][16 mb + i]
+      j -= total - nATp;
+      const int lane = (int)(j % 64), s = (int)((j / 64) % SH);
+      const int mb = (int)((j / (64 * SH)) % MB), k = (int)(j / (64 * SH * MB)) + 1;
+      const int i = lane & 15, g = lane >> 4, ob = s / 4, v = s % 4;
+      double v64 = 0.0, v32 = 0.0;
+      if (k >= 2) {
+        v64 = th_w(th, t, k, 16 * ob + row64(g, v), 16 * mb + i);
+        v32 = th_w(th, t, k, 16 * ob + row32(g, v), 16 * mb + i);
+      }
+      xATp[j] = v64; yATp[j] = (float)v32;
+      continue;
+    }
+    if (j >= total - nATp - nG1) {  // [pb][w][s][lane]: W1_rm W1_rn, pair 16 pb + i, row 16w + row(g, s)
+      j -= total - nATp - nG1;
       const int lane = (int)(j % 64), s = (int)((j / 64) % 4);
       const int w = (int)((j / 256) % MB), pb = (int)(j / (256 * MB));
       const int i = lane & 15, g = lane >> 4, pair = 16 * pb + i;
@@ -910,6 +928,218 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   }
 }
 
+// ---------------------------------------------------------------- two hidden layers, one wave per tile
+// Same outputs as k_mlp_adj for networks with two hidden layers and width up
+// to 32.  One wave owns a whole 16-point tile and every neuron (H/16 row
+// blocks), so the layers chain register to register: the K steps of each
+// product run in the order of the accumulator rows (row(g, v) of block mb),
+// which is where the previous layer's values already sit in the lanes.  No
+// barrier after the weight staging and no exchange through LDS; the layer-2
+// Jacobian feeds no later layer, so it is formed one row block at a time,
+// and the Hessian pairs are accumulated per wave in LDS and written once.
+template <int H, int P, int PR, bool HESS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
+           const double* __restrict__ Kin, double* __restrict__ out) {
+  using E = typename std::conditional<PR == PREC_F64, EngF64, EngF32>::type;
+  using T = typename E::T;
+  using acc_t = typename E::acc;
+  using frag_t = typename E::frag;
+  constexpr int MB = H / 16, P2 = P * (P + 1) / 2;
+  constexpr int SH = H / 4, S1 = (P + 3) / 4, NPB = (P2 + 15) / 16;
+  constexpr int WPB = 4;  // waves, one tile each, per workgroup
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
+
+  __shared__ T W1s[P][H], B2s[P][H], c1s[H], c2s[H], as_[H];
+  __shared__ double hb[HESS ? WPB : 1][HESS ? P2 : 1][16];
+
+  const bool dbl = std::is_same<T, double>::value;
+  {
+    const T* t_W1t = (const T*)(prep + (dbl ? lay.d_W1t : lay.f_W1t));
+    const T* t_Bt = (const T*)(prep + (dbl ? lay.d_Bt : lay.f_Bt));
+    const T* t_c = (const T*)(prep + (dbl ? lay.d_c : lay.f_c));
+    const T* t_a = (const T*)(prep + (dbl ? lay.d_a : lay.f_a));
+    for (int i = tid; i < P * H; i += 64 * WPB) {
+      W1s[i / H][i % H] = t_W1t[i];
+      B2s[i / H][i % H] = t_Bt[(int64_t)P * H + i];
+    }
+    for (int i = tid; i < H; i += 64 * WPB) {
+      c1s[i] = t_c[i];
+      c2s[i] = t_c[H + i];
+      as_[i] = t_a[i];
+    }
+  }
+  __syncthreads();  // the only barrier: every wave reaches it before any exits
+  const int64_t tile = (int64_t)blockIdx.x * WPB + w;
+  if (tile * 16 >= n) return;
+  const int64_t base = tile * 16, qp = base + q;
+  const bool valid = qp < n;
+  const double* d_b = (const double*)(prep + lay.d_b);
+  const frag_t* fW1 = frag_ptr<E>(prep, lay, 0);
+  const frag_t* fA = frag_ptr<E>(prep, lay, 1);
+  const frag_t* fB = frag_ptr<E>(prep, lay, 2);
+  const frag_t* fATp = (const frag_t*)(prep + (dbl ? lay.x_ATp : lay.y_ATp));
+  const frag_t* fG1 = (const frag_t*)(prep + (dbl ? lay.x_G1 : lay.y_G1));
+
+  frag_t kB[S1];
+  double bK = 0.0;  // this lane's share of b . K, in FP64
+#pragma unroll
+  for (int s = 0; s < S1; ++s) {
+    const int m = 4 * s + g;
+    const double kv = (valid && m < P) ? Kin[(int64_t)m * n + qp] : 0.0;
+    kB[s] = (T)kv;
+    if (m < P) bK += d_b[m] * kv;
+  }
+  // ---- layer 1, every row block
+  T z1[MB][4], s1[MB][4], t1[MB][4];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    frag_t a1[S1];
+#pragma unroll
+    for (int s = 0; s < S1; ++s) a1[s] = fW1[(mb * S1 + s) * 64 + lane];
+    const acc_t acc = mma_in<E, P>(a1, kB, zero_acc<E>());
+#pragma unroll
+    for (int v = 0; v < 4; ++v) softplus3((T)(acc[v] + c1s[16 * mb + E::row(g, v)]), z1[mb][v], s1[mb][v], t1[mb][v]);
+  }
+  // ---- layer 2, every row block; value, mu_2 = a F'(y_2), gamma_2 = a F''(y_2)
+  T mu2[MB][4], gam2[MB][4];
+  double val = 0.0;
+#pragma unroll
+  for (int ob = 0; ob < MB; ++ob) {
+    frag_t AV[SH], BV[S1];
+#pragma unroll
+    for (int s = 0; s < SH; ++s) AV[s] = fA[((1 * MB + ob) * SH + s) * 64 + lane];
+#pragma unroll
+    for (int s = 0; s < S1; ++s) BV[s] = fB[((1 * MB + ob) * S1 + s) * 64 + lane];
+    const acc_t acc = mma_in<E, P>(BV, kB, mma_src<E, MB>(AV, z1, zero_acc<E>()));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * ob + E::row(g, v);
+      T f, f1, f2;
+      softplus3((T)(acc[v] + c2s[r]), f, f1, f2);
+      const T a = as_[r];
+      val += (double)(a * f);
+      mu2[ob][v] = a * f1;
+      gam2[ob][v] = a * f2;
+    }
+  }
+  val = group_sum(val) + group_sum(bK);
+  if (g == 0 && valid) out[qp] = val;
+  // ---- reverse: lambda_1 = A_2^T mu_2 (K steps in accumulator-row order)
+  T mu1[MB][4], gam1[MB][4];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    acc_t acc = zero_acc<E>();
+#pragma unroll
+    for (int ob = 0; ob < MB; ++ob)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        acc = E::mma(fATp[((1 * MB + mb) * SH + 4 * ob + v) * 64 + lane], (frag_t)mu2[ob][v], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      mu1[mb][v] = (T)acc[v] * s1[mb][v];
+      gam1[mb][v] = (T)acc[v] * t1[mb][v];
+    }
+  }
+  // ---- gradient: b + W1^T mu_1 + B_2^T mu_2
+  static_for<(P + 3) / 4>([&](auto BI) {
+    constexpr int c0 = decltype(BI)::value * 4;
+    double gp[4];
+    static_for<4>([&](auto JI) {
+      constexpr int j = decltype(JI)::value;
+      T x = (T)0;
+      if constexpr (c0 + j < P) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * mb + E::row(g, v);
+            x += mu1[mb][v] * W1s[c0 + j][r] + mu2[mb][v] * B2s[c0 + j][r];
+          }
+      }
+      gp[j] = (double)x;
+    });
+    const double r = reduce4(gp[0], gp[1], gp[2], gp[3], g);
+    if (c0 + g < P && valid) out[(int64_t)(1 + c0 + g) * n + qp] = r + d_b[c0 + g];
+  });
+  if constexpr (HESS) {
+    // ---- layer-1 Gram on the matrix cores (table rows are packed pair indices)
+#pragma unroll
+    for (int pb = 0; pb < NPB; ++pb) {
+      acc_t acc = zero_acc<E>();
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = E::mma(fG1[((pb * MB + mb) * 4 + s) * 64 + lane], (frag_t)gam1[mb][s], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int pr = 16 * pb + E::row(g, v);
+        if (pr < P2) hb[w][pr][q] = (double)acc[v];
+      }
+    }
+    asm volatile("" ::: "memory");
+    // ---- layer-2 Jacobian, one row block at a time, Gram pairs as columns form
+#pragma unroll 1
+    for (int ob = 0; ob < MB; ++ob) {
+      frag_t AV[SH];
+#pragma unroll
+      for (int s = 0; s < SH; ++s) AV[s] = fA[((1 * MB + ob) * SH + s) * 64 + lane];
+      T g2[4];  // gamma_2 of row block ob, selected without indexing registers at run time
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        g2[v] = gam2[0][v];
+#pragma unroll
+        for (int b = 1; b < MB; ++b) g2[v] = (ob == b) ? gam2[b][v] : g2[v];
+      }
+      // an opaque zero that changes identity every row block, so the
+      // products s_1 W1 below are not hoisted out of this loop (they would
+      // occupy 2 x 9 x 4 registers per lane)
+      int zr = 0;
+      asm volatile("" : "+v"(zr));
+      T J[P][4];
+      double pp[4];
+      auto pair_sum = [&](auto TI) {
+        constexpr int t = decltype(TI)::value;
+        constexpr int m = colmaj_m(t), nn = colmaj_n(t);
+        T x = (T)0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x += g2[v] * J[nn][v] * J[m][v];
+        pp[t % 4] = (double)x;
+        if constexpr (t % 4 == 3 || t == P2 - 1) {
+          constexpr int c0 = t - t % 4;
+#pragma unroll
+          for (int j = t % 4 + 1; j < 4; ++j) pp[j] = 0.0;
+          const double r = reduce4(pp[0], pp[1], pp[2], pp[3], g);
+          constexpr int h0 = packed_index(colmaj_n(c0), colmaj_m(c0), P);
+          constexpr int h1 = (c0 + 1 < P2) ? packed_index(colmaj_n(c0 + 1), colmaj_m(c0 + 1), P) : 0;
+          constexpr int h2 = (c0 + 2 < P2) ? packed_index(colmaj_n(c0 + 2), colmaj_m(c0 + 2), P) : 0;
+          constexpr int h3 = (c0 + 3 < P2) ? packed_index(colmaj_n(c0 + 3), colmaj_m(c0 + 3), P) : 0;
+          const int h = g == 0 ? h0 : g == 1 ? h1 : g == 2 ? h2 : h3;
+          if (c0 + g < P2) hb[w][h][q] += r;
+        }
+      };
+      static_for<P>([&](auto MI) {
+        constexpr int m = decltype(MI)::value;
+        T src[MB][4];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) src[mb][v] = s1[mb][v] * W1s[m][16 * mb + E::row(g, v) + zr];
+        const acc_t acc = mma_src<E, MB>(AV, src, zero_acc<E>());
+#pragma unroll
+        for (int v = 0; v < 4; ++v) J[m][v] = (T)acc[v] + B2s[m][16 * ob + E::row(g, v)];
+        static_for<m + 1>([&](auto NI) { pair_sum(std::integral_constant<int, m * (m + 1) / 2 + decltype(NI)::value>{}); });
+      });
+    }
+    asm volatile("" ::: "memory");
+    // ---- the tile's Hessian: 16 consecutive points per packed pair
+    for (int i = lane; i < P2 * 16; i += 64) {
+      const int h = i / 16, qq = i % 16;
+      if (base + qq < n) out[(int64_t)(1 + P + h) * n + base + qq] = hb[w][h][qq];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- dispatch
 template <int H, int L, int P>
 static int launch_mlp_t(const PrepLayout& lay, int prec, const unsigned char* prep, int64_t n,
@@ -969,9 +1199,29 @@ static void launch_adj_one(const PrepLayout& lay, const unsigned char* prep, int
   k_mlp_adj<H, L, P, PR, HESS><<<grid, block, 0, s>>>(prep, lay, n, K, out);
 }
 
+template <int H, int P, int PR, bool HESS>
+static void launch_adj2_one(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
+                            double* out, hipStream_t s) {
+  const unsigned grid = (unsigned)(((n + 15) / 16 + 3) / 4);
+  k_mlp_adj2<H, P, PR, HESS><<<grid, 256, 0, s>>>(prep, lay, n, K, out);
+}
+
 template <int H, int L, int P>
 static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char* prep, int64_t n,
                             const double* K, double* out, int hess, hipStream_t s) {
+  if constexpr (L == 2 && H <= 32) {
+    switch (prec) {
+      case PREC_F64:
+        if (hess) launch_adj2_one<H, P, PREC_F64, true>(lay, prep, n, K, out, s);
+        else launch_adj2_one<H, P, PREC_F64, false>(lay, prep, n, K, out, s);
+        return 0;
+      case PREC_F32:
+        if (hess) launch_adj2_one<H, P, PREC_F32, true>(lay, prep, n, K, out, s);
+        else launch_adj2_one<H, P, PREC_F32, false>(lay, prep, n, K, out, s);
+        return 0;
+      default: return -2;
+    }
+  }
   switch (prec) {
     case PREC_F64:
       if (hess) launch_adj_one<H, L, P, PREC_F64, true>(lay, prep, n, K, out, s);

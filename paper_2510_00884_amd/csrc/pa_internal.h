@@ -30,6 +30,7 @@ struct PrepLayout {
   int64_t z_W1, z_A, z_B;
   int64_t x_AT, y_AT;   // transposed hidden weights for reverse products [L][MB][SH][64]
   int64_t x_G1, y_G1;   // layer-1 Gram table W1_rm W1_rn as MFMA A fragments [NPB][MB][4][64]
+  int64_t x_ATp, y_ATp; // transposed hidden weights, K steps in accumulator-row order [L][MB][SH][64]
   int64_t k0, nout;
   int64_t total;
 };
