@@ -109,19 +109,135 @@ def cpu_baseline(X, conn, u, theta, p, h, L, Av, n_sample):
     """The oracle (plain FP64 NumPy, single thread) on a contiguous sample of
     elements: element residual/stiffness through the push-forward route and
     COO->CSR assembly of that sample."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import fe, ncm
     om = ncm.model_from_theta(theta, p, h, L, Av, normalize=True)
     sub = conn[:n_sample]
-    t0 = time.perf_counter()
-    dNdX, w, _ = fe.geometry(X, sub)
-    r_e, K_e, _ = fe.element_residual_stiffness(u, sub, dNdX, w, om)
-    fe.assemble(sub, r_e, K_e, X.shape[0])
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):  # BLAS pools pinned to one thread: the figure is one core's
+        t0 = time.perf_counter()
+        dNdX, w, _ = fe.geometry(X, sub)
+        r_e, K_e, _ = fe.element_residual_stiffness(u, sub, dNdX, w, om)
+        fe.assemble(sub, r_e, K_e, X.shape[0])
+        dt = time.perf_counter() - t0
     nq = dNdX.shape[1]
     return {"value": n_sample * nq / dt, "unit": "qp evals/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_sample} elements ({n_sample * nq} points) of the same mesh, model and "
                       f"displacement; geometry + element residual/stiffness + assembly; {dt:.1f} s; "
                       f"NumPy single thread on {os.cpu_count()} host cores"}
+
+
+def _profiled(lib, fn, steps, warmup):
+    """ms per call of fn (HIP events on the current stream) and the library's
+    per-kernel times."""
+    import ctypes as C
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    lib.pa_profile_enable(1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    lib.pa_profile_enable(0)
+    kern = {}
+    for i in range(lib.pa_profile_count()):
+        nm, t, k = C.c_char_p(), C.c_double(), C.c_int64()
+        lib.pa_profile_get(i, C.byref(nm), C.byref(t), C.byref(k))
+        kern[nm.value.decode()] = round(t.value / max(k.value, 1), 4)
+    return e0.elapsed_time(e1) / steps, kern
+
+
+def other_workload(args):
+    """The point-batch, calibration and large-mesh workloads (not the
+    default bench line): prints one JSON line per workload."""
+    import torch
+    from paper_2510_00884_amd import api, synth
+    from paper_2510_00884_amd import _lib as L
+    lib = L.load()
+    n_sv, h, Lh = 2, 64, 3
+    p = synth.num_inputs(n_sv)
+    Av = synth.structural_vectors(n_sv)
+    theta = synth.micnn_params(p, h, Lh, seed=1)
+    steps, warmup = max(args.steps // 4, 2), 1
+    if args.workload == "points_2pow22":
+        n = 1 << 22
+        F = torch.tensor(synth.sample_F(n, seed=0), device="cuda")
+        res = {}
+        ref = None
+        for prec, algo in [("fp64", "adjoint"), ("fp32", "adjoint"), ("bf16", "forward"), ("bf16_corr", "forward"),
+                           ("fp64", "forward")]:
+            gm = api.Model(theta, n_sv, h, Lh, A=Av, normalize=True, algorithm=algo)
+            bufs = {}
+            def call():
+                bufs["out"] = api.energy_stress_tangent(gm, F, prec=prec)
+            ms, kern = _profiled(lib, call, steps, warmup)
+            out = bufs["out"]
+            if ref is None:
+                ref = {k: v.clone() for k, v in out.items()}
+            err = {k: ((out[k] - ref[k]).norm() / ref[k].norm()).item() for k in ("psi", "P", "A")}
+            res[f"{prec}/{algo}"] = {"ms": ms, "qp_per_s": n / (ms / 1e3), "kernels_ms": kern,
+                                     "rel_err_vs_fp64": err}
+            print(f"[bench] {prec}/{algo}: {ms:.3f} ms, {n / (ms / 1e3):.3e} qp/s", file=sys.stderr, flush=True)
+            del out
+            bufs.clear()
+        best = res["fp64/adjoint"]
+        line = {"metric": "qp evals/s (Psi+P+tangent) & elements assembled/s, FP64 vs FP32/BF16 at stated error",
+                "value": best["qp_per_s"], "unit": "qp evals/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+                "ms_per_step": best["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f64", "data": "synthetic",
+                "config": {"workload": "2^22 independent points, orthotropic (9 inputs), MICNN 3x64 softplus: "
+                                       "Psi, P and dP/dF per point"},
+                "precisions": res}
+    elif args.workload == "calib_2pow20":
+        n = 1 << 20
+        F = torch.tensor(synth.sample_F(n, seed=3), device="cuda")
+        Pbar = torch.tensor(synth.rng(7).normal(size=(n, 9)) / n, device="cuda")
+        gm = api.Model(theta, n_sv, h, Lh, A=Av, normalize=False, algorithm="adjoint")
+        res = {}
+        for prec in ("fp32", "fp64"):
+            ms_f, kf = _profiled(lib, lambda: api.energy_stress_tangent(gm, F, prec=prec, psi=False, A=False),
+                                 steps, warmup)
+            ms_b, kb = _profiled(lib, lambda: api.param_backward(gm, F, Pbar, prec=prec), steps, warmup)
+            res[prec] = {"forward_P_ms": ms_f, "adjoint_ms": ms_b, "step_ms": ms_f + ms_b,
+                         "kernels_ms": {**kf, **kb}}
+            print(f"[bench] calibration {prec}: forward {ms_f:.3f} ms + adjoint {ms_b:.3f} ms",
+                  file=sys.stderr, flush=True)
+        st = res["fp32"]["step_ms"]
+        line = {"metric": "calibration samples/s (stress forward + parameter adjoint)", "value": n / (st / 1e3),
+                "unit": "samples/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": st,
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                "data": "synthetic",
+                "config": {"workload": "2^20-point stress calibration, MICNN 3x64 softplus, FP32 network"},
+                "precisions": res}
+    else:  # tet10_56
+        n = 56
+        X, conn, par = synth.tet10_mesh(n)
+        u = torch.tensor(synth.displacement_modes(X, 1.0 / n, seed=0), device="cuda").reshape(-1)
+        gm = api.Model(theta, n_sv, h, Lh, A=Av, normalize=True, algorithm="adjoint")
+        mesh = api.FEMesh(X, conn, colour=par)
+        ws = torch.empty(mesh.workspace_bytes(gm, "gather"), dtype=torch.uint8, device="cuda")
+        bufs = {}
+        res = {}
+        for prec in ("fp32", "fp64"):
+            ms, kern = _profiled(lib, lambda: api.tangent_build(gm, mesh, u, prec=prec, workspace=ws, bufs=bufs),
+                                 steps, warmup)
+            res[prec] = {"ms": ms, "qp_per_s": mesh.n_el * mesh.nq / (ms / 1e3), "kernels_ms": kern}
+            print(f"[bench] tet10 {prec}: {ms:.3f} ms", file=sys.stderr, flush=True)
+        ms = res["fp32"]["ms"]
+        line = {"metric": "qp evals/s (Psi+P+tangent) & elements assembled/s, FP64 vs FP32/BF16 at stated error",
+                "value": mesh.n_el * mesh.nq / (ms / 1e3), "unit": "qp evals/s", "n_gpus": 1, "steps": steps,
+                "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f32 network, f64 elsewhere", "data": "synthetic",
+                "config": {"workload": f"tet10 Kuhn mesh of {n}^3 cubes ({mesh.n_el} elements, "
+                                       f"{3 * mesh.n_nodes} dofs, {mesh.nnz} nonzeros), MICNN 3x64 softplus, "
+                                       "one Newton tangent build"},
+                "elements_per_s": mesh.n_el / (ms / 1e3), "precisions": res}
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -135,6 +251,10 @@ def main():
                     help="network Hessian formation (BF16 variants always use forward)")
     ap.add_argument("--variants", default="fp32,bf16,bf16_corr",
                     help="other precisions timed after the headline run ('' for none)")
+    ap.add_argument("--workload", default="hex8_64",
+                    choices=["hex8_64", "points_2pow22", "calib_2pow20", "tet10_56"],
+                    help="hex8_64 (default): the tangent-build bench line; the others measure the point-batch "
+                         "precision ladder, the calibration step and the large tet10 mesh")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -165,6 +285,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": nb, "copy_probe_bytes_written": nb, "launches": 3}), flush=True)
+        return
+    if args.workload != "hex8_64":
+        other_workload(args)
         return
     n = args.n
     n_sv, h, Lh = 2, 32, 2
