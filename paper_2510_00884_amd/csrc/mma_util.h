@@ -96,26 +96,48 @@ __device__ constexpr int hess_n(int h, int P) {
 
 template <class E> __device__ inline typename E::acc zero_acc() { return typename E::acc{0, 0, 0, 0}; }
 
-// Sum a per-lane partial over the four lane groups (rows) of the wave.
-__device__ inline double group_sum(double x) {
-  x += __shfl_xor(x, 16);
-  x += __shfl_xor(x, 32);
-  return x;
+// Exchanges between lane halves on gfx950 (checked on the device):
+// swap32(a, b) leaves a = [a lanes 0-31, b lanes 0-31] and
+// b = [a lanes 32-63, b lanes 32-63]; swap16(a, b) does the same with the
+// 16-lane rows, a = [a.r0, b.r0, a.r2, b.r2], b = [a.r1, b.r1, a.r3, b.r3].
+// A double moves as its two dwords.
+__device__ inline void swap32(double& a, double& b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(double, (unsigned long long)lo[0] | ((unsigned long long)hi[0] << 32));
+  b = __builtin_bit_cast(double, (unsigned long long)lo[1] | ((unsigned long long)hi[1] << 32));
+}
+__device__ inline void swap16(double& a, double& b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(double, (unsigned long long)lo[0] | ((unsigned long long)hi[0] << 32));
+  b = __builtin_bit_cast(double, (unsigned long long)lo[1] | ((unsigned long long)hi[1] << 32));
 }
 
+// Sum a per-lane partial over the four lane groups (rows) of the wave; every
+// lane receives the sum for its column.  All 64 lanes must be active.
+__device__ inline double group_sum(double x) {
+  double y = x;
+  swap32(x, y);  // x = [r0, r1, r0, r1], y = [r2, r3, r2, r3]
+  double s = x + y, t = s;
+  swap16(s, t);  // s = [c01, c01, c23, c23] halves ... summed below
+  return s + t;
+}
 
 // Sum four per-lane partials p0..p3 (one per column) over the four lane
 // groups of a wave.  On return lane group g holds the full sum of column g
-// for its point (three exchanges instead of eight).
+// for its point.  All 64 lanes must be active.
 __device__ inline double reduce4(double p0, double p1, double p2, double p3, int g) {
-  const bool lo = (g & 2) == 0;
-  const double r0 = __shfl_xor(lo ? p2 : p0, 32);
-  const double r1 = __shfl_xor(lo ? p3 : p1, 32);
-  const double k0 = (lo ? p0 : p2) + r0;
-  const double k1 = (lo ? p1 : p3) + r1;
-  const bool even = (g & 1) == 0;
-  const double r = __shfl_xor(even ? k1 : k0, 16);
-  return (even ? k0 : k1) + r;
+  (void)g;
+  swap32(p0, p2);  // p0 = [p0.r0, p0.r1, p2.r0, p2.r1], p2 = [p0.r2, p0.r3, p2.r2, p2.r3]
+  swap32(p1, p3);
+  double k0 = p0 + p2, k1 = p1 + p3;  // rows: [col0 (r0+r2), col0 (r1+r3), col2 .., col2 ..], col1/col3 likewise
+  swap16(k0, k1);  // k0 = [k0.r0, k1.r0, k0.r2, k1.r2], k1 = [k0.r1, k1.r1, k0.r3, k1.r3]
+  return k0 + k1;
 }
 
 // Sum over the 16 lanes that share a lane group (the 16 points of a tile).
