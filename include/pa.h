@@ -268,6 +268,33 @@ int pa_param_backward(const pa_model_desc* desc, const void* prepared, int prec,
                       const double* F, const double* P_bar, double* theta_bar,
                       void* workspace, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- residual loss */
+/* The NN-EUCLID residual loss of eq. (loss) (Sec. "Data generation and NCM
+ * training") for one time step, and its cotangent in the residual:
+ *   L = sum_{d free} r_d^2 + sum_b (R_b - sum_{d in boundary b} r_d)^2,
+ *   r_bar_d = dL/dr_d = 2 r_d (free), -2 (R_b - sum_{boundary b} r) (d on b).
+ * r [n_rows]: assembled residual (node-major dofs); dof_group [n_rows] int32:
+ * -1 = free (D^free), b in [0, n_groups) = constrained dof of reaction
+ * boundary b (D^fix_b), -2 = constrained and not observed.  R: device
+ * [n_groups] reaction forces.  loss: device [1] or NULL; r_bar [n_rows] or
+ * NULL.  The sums are reduced in a fixed order (bitwise reproducible).
+ * n_groups <= 63.  Over several time steps, sum the losses and the
+ * parameter gradients. */
+size_t pa_residual_loss_workspace(int64_t n_rows, int32_t n_groups);
+int pa_residual_loss(int64_t n_rows, const double* r, const int32_t* dof_group, int32_t n_groups,
+                     const double* R, double* loss, double* r_bar, void* workspace, size_t ws_bytes,
+                     void* stream);
+/* Parameter gradient of a residual cotangent: theta_bar = (dr/dtheta)^T r_bar
+ * for the raw network (normalize must be 0).  Since r^a_i = sum_q w P_iJ
+ * G^a_J (eq. r-quad), the stress cotangent is P_bar_q = w_q sum_a
+ * r_bar[a] (x) G^a_q, followed by pa_param_backward at the points' F.
+ * u [3 n_nodes]; r_bar [3 n_nodes]; theta_bar [n_params] overwritten.
+ * prec: PA_FP64 or PA_FP32. */
+size_t pa_residual_param_backward_workspace(const pa_model_desc* desc, const pa_mesh* mesh, int prec);
+int pa_residual_param_backward(const pa_model_desc* desc, const void* prepared, int prec, const pa_mesh* mesh,
+                               const double* u, const double* r_bar, double* theta_bar, void* workspace,
+                               size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- profiling */
 /* Per-kernel timing with HIP events recorded on the launch stream around
  * every kernel the library launches (off by default).  pa_profile_enable(1)

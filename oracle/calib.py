@@ -100,3 +100,53 @@ def loss(theta, F, P_target, Avec, p, h, L, has_bias=True, normalize=False):
     _, dN, _ = ncm.micnn(K.astype(np.result_type(K, theta)), model.hidden, model.a, model.b)
     P = np.einsum("nm,nmiJ->niJ", dN, g)
     return np.sum((P - P_target) ** 2) / F.shape[0]
+
+
+# ----------------------------------------------------------------------------
+# residual (NN-EUCLID) loss, eq. (loss), one time step
+# ----------------------------------------------------------------------------
+def _residual_loss_value(r, dof_group, R, xp):
+    """L = sum_{free} r_d^2 + sum_b (R_b - sum_{d in b} r_d)^2 (eq. loss);
+    dof_group: -1 free, b >= 0 reaction boundary b, -2 constrained unobserved."""
+    free = dof_group == -1
+    L = (r[free] ** 2).sum()
+    for b in range(len(R)):
+        L = L + (R[b] - r[dof_group == b].sum()) ** 2
+    return L
+
+
+def residual_loss_and_grad(theta, X, conn, u, dof_group, R, Avec, p, h, L, has_bias=True):
+    """L and dL/dtheta for the raw network (numpy in, numpy out): the
+    residual r^a_i = sum_q w P_iJ(F_q; theta) dN^a/dX_J (eqs. r-quad,
+    apprx-r, material form) assembled over node-major dofs with PyTorch on
+    the CPU in FP64, the stress from stress_from_theta, and reverse-mode
+    automatic differentiation for the gradient."""
+    from . import fe
+    dNdX, w, _ = fe.geometry(X, conn)                       # (n_el, nq, nen, 3), (n_el, nq)
+    F = fe.deformation_gradients(u, conn, dNdX)             # (n_el, nq, 3, 3)
+    n_el, nq = F.shape[:2]
+    K, g = feature_grads(F.reshape(-1, 3, 3), Avec)
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    P = stress_from_theta(th, torch.tensor(K), torch.tensor(g), p, h, L, has_bias).reshape(n_el, nq, 3, 3)
+    G = torch.tensor(dNdX)
+    wt = torch.tensor(w)
+    r_e = torch.einsum("eq,eqiJ,eqaJ->eai", wt, P, G)      # (n_el, nen, 3)
+    dofs = torch.tensor(fe.element_dofs(conn)).reshape(-1)
+    r = torch.zeros(3 * X.shape[0], dtype=torch.float64).index_add(0, dofs, r_e.reshape(-1))
+    Lval = _residual_loss_value(r, torch.tensor(dof_group), torch.tensor(np.asarray(R, dtype=np.float64)), torch)
+    grad, = torch.autograd.grad(Lval, th)
+    return float(Lval.detach()), grad.numpy(), r.detach().numpy()
+
+
+def residual_loss(theta, X, conn, u, dof_group, R, Avec, p, h, L, has_bias=True):
+    """L through the NumPy model and the oracle's element residual (spatial
+    form); real or complex theta, for finite-difference and complex-step
+    pins."""
+    from . import fe
+    model = ncm.model_from_theta(theta, p, h, L, Avec, normalize=False, has_bias=has_bias)
+    dNdX, w, _ = fe.geometry(X, conn)
+    r_e, _, _ = fe.element_residual_stiffness(u, conn, dNdX, w, model)
+    dofs = fe.element_dofs(conn)
+    r = np.zeros(3 * X.shape[0], dtype=np.result_type(r_e, np.float64))
+    np.add.at(r, dofs.reshape(-1), r_e.reshape(-1))
+    return _residual_loss_value(r, np.asarray(dof_group), np.asarray(R), np)

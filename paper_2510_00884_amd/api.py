@@ -291,6 +291,45 @@ def tangent_build(model: Model, mesh: FEMesh, u, prec="fp64", workspace=None, bu
     return r, vals
 
 
+def residual_loss(r, dof_group, R):
+    """Residual loss of eq. (loss) for one time step and its cotangent:
+    returns (L (1,) tensor, r_bar).  dof_group: int32 per dof, -1 free, b >= 0
+    reaction boundary b, -2 constrained and unobserved; R: reaction forces."""
+    lib = L.load()
+    r = r.reshape(-1).contiguous()
+    grp = dof_group.to(device=r.device, dtype=torch.int32).contiguous()
+    Rt = torch.as_tensor(R, dtype=torch.float64, device=r.device).reshape(-1).contiguous()
+    nb = lib.pa_residual_loss_workspace(r.numel(), Rt.numel())
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=r.device)
+    loss = torch.empty(1, dtype=torch.float64, device=r.device)
+    rbar = torch.empty_like(r)
+    L.check(lib.pa_residual_loss(r.numel(), _p(r), _p(grp), Rt.numel(), _p(Rt), _p(loss), _p(rbar), _p(ws),
+                                 ws.numel(), _stream()), "pa_residual_loss")
+    return loss, rbar
+
+
+def residual_param_backward(model: Model, mesh: FEMesh, u, r_bar, prec="fp64"):
+    """theta_bar = (dr/dtheta)^T r_bar for the raw network."""
+    u = u.reshape(-1).contiguous()
+    rb = r_bar.reshape(-1).contiguous()
+    out = torch.empty(model.n_params, dtype=torch.float64, device=u.device)
+    nb = model.lib.pa_residual_param_backward_workspace(C.byref(model.desc), C.byref(mesh.c_mesh), _prec(prec))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=u.device)
+    L.check(model.lib.pa_residual_param_backward(C.byref(model.desc), _p(model.prepared), _prec(prec),
+                                                 C.byref(mesh.c_mesh), _p(u), _p(rb), _p(out), _p(ws), ws.numel(),
+                                                 _stream()), "pa_residual_param_backward")
+    return out
+
+
+def residual_loss_and_grad(model: Model, mesh: FEMesh, u, dof_group, R, prec="fp64"):
+    """Loss of eq. (loss) for one time step and its gradient in theta: the
+    residual from the tangent build (node-centric assembly), the loss and
+    its cotangent, then the residual's parameter adjoint."""
+    r, _ = tangent_build(model, mesh, u, prec=prec, assembly="gather")
+    loss, rbar = residual_loss(r, dof_group, R)
+    return loss, residual_param_backward(model, mesh, u, rbar, prec)
+
+
 def param_backward(model: Model, F, P_bar, prec="fp32", soa=False, workspace=None):
     """theta_bar = sum_q (dP_q/dtheta)^T P_bar_q (raw network)."""
     Fs = F if soa else _soa9(F)

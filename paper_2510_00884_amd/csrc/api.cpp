@@ -411,6 +411,73 @@ int pa_tangent_build_gather(const pa_model_desc* d, const void* prepared, int pr
   return hip_check("pa_tangent_build_gather");
 }
 
+size_t pa_residual_loss_workspace(int64_t n_rows, int32_t n_groups) {
+  if (n_rows < 0 || n_groups < 0 || n_groups > 63) return 0;
+  return (size_t)(al(8 * (int64_t)loss_partial_blocks(n_rows) * (n_groups + 1)) + al(8 * (int64_t)(n_groups + 1)));
+}
+
+int pa_residual_loss(int64_t n_rows, const double* r, const int32_t* dof_group, int32_t n_groups, const double* R,
+                     double* loss, double* r_bar, void* workspace, size_t ws_bytes, void* stream) {
+  if (n_rows < 0 || n_groups < 0 || n_groups > 63) return fail(PA_ERR_ARG, "n_rows < 0 or n_groups outside [0, 63]");
+  if ((n_rows > 0 && (!r || !dof_group)) || (n_groups > 0 && !R)) return fail(PA_ERR_ARG, "NULL argument");
+  if (!loss && !r_bar) return fail(PA_ERR_ARG, "nothing to compute");
+  const int64_t need = (int64_t)pa_residual_loss_workspace(n_rows, n_groups);
+  if (!workspace || (int64_t)ws_bytes < need) return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
+  unsigned char* ws = (unsigned char*)workspace;
+  double* partials = (double*)ws;
+  double* sums = (double*)(ws + al(8 * (int64_t)loss_partial_blocks(n_rows) * (n_groups + 1)));
+  hipStream_t s = S(stream);
+  {
+    Prof pr("residual_loss", s);
+    if (launch_residual_loss(n_rows, r, dof_group, n_groups, R, partials, sums, loss, r_bar, s))
+      return fail(PA_ERR_ARG, "residual loss launch failed");
+  }
+  return hip_check("pa_residual_loss");
+}
+
+size_t pa_residual_param_backward_workspace(const pa_model_desc* d, const pa_mesh* m, int prec) {
+  if (!d || !m || d->n_sv < 0 || d->n_sv > 2 || d->width <= 0) return 0;
+  const int64_t n = m->n_el * m->nq;
+  return (size_t)(al(8 * 9 * n) + al(8 * 9 * n) + param_backward_ws(d->width, d->n_hidden, p_of(d), prec, n));
+}
+
+int pa_residual_param_backward(const pa_model_desc* d, const void* prepared, int prec, const pa_mesh* m,
+                               const double* u, const double* r_bar, double* theta_bar, void* workspace,
+                               size_t ws_bytes, void* stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (prec != PA_FP64 && prec != PA_FP32) return fail(PA_ERR_UNSUPPORTED, "supports PA_FP64 and PA_FP32");
+  if (d->normalize) return fail(PA_ERR_UNSUPPORTED, "differentiates the raw network (normalize = 0)");
+  if ((rc = check_mesh(m))) return rc;
+  if (!prepared || !theta_bar || (m->n_el > 0 && (!u || !r_bar))) return fail(PA_ERR_ARG, "NULL argument");
+  const int64_t n = m->n_el * m->nq;
+  const int64_t need = (int64_t)pa_residual_param_backward_workspace(d, m, prec);
+  if (!workspace || (int64_t)ws_bytes < need) return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
+  hipStream_t s = S(stream);
+  unsigned char* ws = (unsigned char*)workspace;
+  double* F = (double*)ws;
+  double* Pbar = (double*)(ws + al(8 * 9 * n));
+  unsigned char* bws = ws + al(8 * 9 * n) + al(8 * 9 * n);
+  {
+    Prof pr("gather_F", s);
+    launch_gather_F(m->nen, m->nq, m->n_el, m->conn, m->dNdX, u, F, s);
+  }
+  {
+    Prof pr("residual_cotangent", s);
+    launch_residual_cotangent(m->nen, m->n_el, m->conn, m->dNdX, m->w, r_bar, Pbar, s);
+  }
+  const PrepLayout lay = layout_of(d);
+  const ThetaLayout tl = theta_layout(d->width, d->n_hidden, p_of(d), d->has_bias ? 1 : 0);
+  {
+    Prof pr("param_backward", s);
+    rc = launch_param_backward(lay, tl, d->n_sv, prec, (const unsigned char*)prepared, model_const(d), n, F, Pbar,
+                               theta_bar, bws, s);
+  }
+  if (rc == -2) return fail(PA_ERR_UNSUPPORTED, "no adjoint kernel for this configuration");
+  if (rc) return fail(PA_ERR_ARG, "pa_residual_param_backward failed (%d)", rc);
+  return hip_check("pa_residual_param_backward");
+}
+
 int pa_node_incidence(int32_t nen, int64_t n_el, int64_t n_nodes, const int32_t* conn_host, int64_t* ptr,
                       int32_t* ent) {
   if (nen != 8 && nen != 10) return fail(PA_ERR_ARG, "nen must be 8 or 10");

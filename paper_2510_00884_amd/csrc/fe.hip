@@ -137,6 +137,102 @@ __global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, const int32_t* _
   for (int c = 0; c < 9; ++c) F[(int64_t)c * n + t] = f[c];
 }
 
+// ---------------------------------------------------------------- residual-loss cotangent
+// Reverse of r^a_i = sum_q w P_iJ G^a_J (eq. r-quad, material form): for a
+// residual cotangent rbar (node-major dofs), the stress cotangent at point
+// (q, e) is  Pbar_iJ = w sum_a rbar[3 conn_a + i] G^a_J.  Point index
+// q * n_el + e, output [9][n_el nq].
+template <int NEN>
+__global__ void __launch_bounds__(256) k_residual_cotangent(int64_t n_el, const int32_t* __restrict__ conn,
+                                                            const double* __restrict__ dNdX,
+                                                            const double* __restrict__ w,
+                                                            const double* __restrict__ rbar,
+                                                            double* __restrict__ Pbar) {
+  constexpr int NQ = nq_of<NEN>();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = n_el * NQ;
+  if (t >= n) return;
+  const int q = (int)(t / n_el);
+  const int64_t e = t % n_el;
+  double f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < NEN; ++a) {
+    const int64_t node = conn[(int64_t)a * n_el + e];
+    const double r0 = rbar[3 * node], r1 = rbar[3 * node + 1], r2 = rbar[3 * node + 2];
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      const double gv = dNdX[(((int64_t)q * NEN + a) * 3 + J) * n_el + e];
+      f[J] += r0 * gv;
+      f[3 + J] += r1 * gv;
+      f[6 + J] += r2 * gv;
+    }
+  }
+  const double wq = w[t];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) Pbar[(int64_t)c * n + t] = wq * f[c];
+}
+
+// Residual loss of eq. (loss) for one time step: dof d is free (group -1),
+// fixed on reaction boundary b (group b >= 0) or fixed and unobserved
+// (group -2).  L = sum_free r_d^2 + sum_b (R_b - sum_{d in b} r_d)^2.
+// Pass 1: per-workgroup partial sums (free squares, then one sum per
+// boundary) in a fixed order; pass 2: one workgroup sums the partials in
+// workgroup order (bitwise reproducible) and forms L; pass 3: the cotangent
+// rbar_d = 2 r_d (free), -2 (R_b - S_b) (boundary b), 0 otherwise.
+constexpr int LOSS_BLOCK = 256;
+__global__ void __launch_bounds__(LOSS_BLOCK) k_loss_partials(int64_t n_rows, const double* __restrict__ r,
+                                                              const int32_t* __restrict__ group, int n_groups,
+                                                              double* __restrict__ partials) {
+  __shared__ double red[LOSS_BLOCK];
+  const int tid = threadIdx.x;
+  for (int k = -1; k < n_groups; ++k) {  // k = -1: free squares
+    double acc = 0.0;
+    for (int64_t d = (int64_t)blockIdx.x * LOSS_BLOCK + tid; d < n_rows; d += (int64_t)gridDim.x * LOSS_BLOCK) {
+      const int gdof = group[d];
+      if (gdof == k) acc += (k < 0) ? r[d] * r[d] : r[d];
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = LOSS_BLOCK / 2; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    if (tid == 0) partials[(int64_t)blockIdx.x * (n_groups + 1) + (k + 1)] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(64) k_loss_finish(int nblk, int n_groups, const double* __restrict__ partials,
+                                                    const double* __restrict__ R, double* __restrict__ sums,
+                                                    double* __restrict__ loss) {
+  // one thread per column, partials summed in workgroup order
+  const int k = threadIdx.x;
+  if (k <= n_groups) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partials[(int64_t)b * (n_groups + 1) + k];
+    sums[k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double L = sums[0];
+    for (int b = 0; b < n_groups; ++b) {
+      const double m = R[b] - sums[1 + b];
+      L += m * m;
+    }
+    if (loss) loss[0] = L;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_loss_rbar(int64_t n_rows, const double* __restrict__ r,
+                                                   const int32_t* __restrict__ group,
+                                                   const double* __restrict__ R, const double* __restrict__ sums,
+                                                   double* __restrict__ rbar) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n_rows) return;
+  const int gdof = group[d];
+  rbar[d] = (gdof == -1) ? 2.0 * r[d] : (gdof >= 0) ? -2.0 * (R[gdof] - sums[1 + gdof]) : 0.0;
+}
+
 // ---------------------------------------------------------------- chain rule + integration
 // Element kernel over a block of E = 8 elements, 3 nen threads per element:
 //  phase A (one thread per point q and row i of its tangent): from F,
@@ -507,6 +603,30 @@ int launch_assemble(int nen, int64_t e_begin, int64_t e_count, const int32_t* pe
   PA_NEN_SWITCH(nen,
                 (k_assemble<8><<<nblocks(e_count * 24, 256), 256, 0, s>>>(e_begin, e_count, perm, n_el, conn, row_ptr, e2csr, r_e, K_e, r, vals)),
                 (k_assemble<10><<<nblocks(e_count * 30, 256), 256, 0, s>>>(e_begin, e_count, perm, n_el, conn, row_ptr, e2csr, r_e, K_e, r, vals)));
+  return 0;
+}
+
+int launch_residual_cotangent(int nen, int64_t n_el, const int32_t* conn, const double* dNdX, const double* w,
+                              const double* rbar, double* Pbar, hipStream_t s) {
+  if (n_el == 0) return 0;
+  const int nq = nen == 8 ? 8 : 4;
+  PA_NEN_SWITCH(nen, (k_residual_cotangent<8><<<nblocks(n_el * nq, 256), 256, 0, s>>>(n_el, conn, dNdX, w, rbar, Pbar)),
+                (k_residual_cotangent<10><<<nblocks(n_el * nq, 256), 256, 0, s>>>(n_el, conn, dNdX, w, rbar, Pbar)));
+  return 0;
+}
+
+int loss_partial_blocks(int64_t n_rows) {
+  const int64_t b = (n_rows + LOSS_BLOCK - 1) / LOSS_BLOCK;
+  return (int)(b < 1024 ? (b > 0 ? b : 1) : 1024);
+}
+
+int launch_residual_loss(int64_t n_rows, const double* r, const int32_t* group, int n_groups, const double* R,
+                         double* partials, double* sums, double* loss, double* rbar, hipStream_t s) {
+  if (n_groups < 0 || n_groups > 63) return -1;
+  const int nb = loss_partial_blocks(n_rows);
+  k_loss_partials<<<nb, LOSS_BLOCK, 0, s>>>(n_rows, r, group, n_groups, partials);
+  k_loss_finish<<<1, 64, 0, s>>>(nb, n_groups, partials, R, sums, loss);
+  if (rbar && n_rows > 0) k_loss_rbar<<<nblocks(n_rows, 256), 256, 0, s>>>(n_rows, r, group, R, sums, rbar);
   return 0;
 }
 

@@ -87,5 +87,10 @@ int launch_assemble(int nen, int64_t e_begin, int64_t e_count, const int32_t* pe
                     const int32_t* conn, const int64_t* row_ptr, const int32_t* e2csr,
                     const double* r_e, const double* K_e, double* r, double* vals, hipStream_t s);
 int launch_fill(double* x, int64_t n, double v, hipStream_t s);
+int launch_residual_cotangent(int nen, int64_t n_el, const int32_t* conn, const double* dNdX, const double* w,
+                              const double* rbar, double* Pbar, hipStream_t s);
+int loss_partial_blocks(int64_t n_rows);
+int launch_residual_loss(int64_t n_rows, const double* r, const int32_t* group, int n_groups, const double* R,
+                         double* partials, double* sums, double* loss, double* rbar, hipStream_t s);
 
 }  // namespace pa

@@ -240,3 +240,19 @@ def loading_path(kind: str, gamma: float) -> np.ndarray:
     else:
         raise ValueError(kind)
     return F
+
+
+def reaction_groups(X: np.ndarray, tol: float = 1e-12):
+    """Dof classes for the residual loss on a unit-cube mesh: the X_0 = 0
+    face is clamped and unobserved (-2); on the X_0 = 1 face the dofs in
+    direction 0 form reaction boundary 0; on the X_1 = 1 face the dofs in
+    direction 1 form reaction boundary 1 (where not already taken); every
+    other dof is free (-1).  Returns int32 [3 n_nodes], node-major."""
+    n = X.shape[0]
+    grp = np.full((n, 3), -1, dtype=np.int32)
+    x1 = np.abs(X[:, 1] - 1.0) < tol
+    grp[x1, 1] = 1
+    x0 = np.abs(X[:, 0] - 1.0) < tol
+    grp[x0, 0] = 0
+    grp[np.abs(X[:, 0]) < tol, :] = -2
+    return grp.reshape(-1)

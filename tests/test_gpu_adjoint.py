@@ -97,3 +97,48 @@ def test_autograd_function_and_finite_differences():
         e[i] = hstep
         fd = (gpu_loss(theta + e) - gpu_loss(theta - e)) / (2 * hstep)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, np.abs(g).max()), (i, fd, g[i])
+
+
+@pytest.mark.parametrize("kind,n,n_sv,h,L", [("hex8", 3, 2, 32, 2), ("tet10", 2, 1, 16, 3)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_residual_loss_gradient(kind, n, n_sv, h, L, prec, tol):
+    """Loss of eq. (loss) and its parameter gradient through the GPU path
+    (tangent build, loss cotangent, residual cotangent, parameter adjoint)
+    against the oracle's reverse-mode gradient."""
+    api = need_gpu()
+    say("residual loss gradient", kind, n, n_sv, h, L, prec)
+    X, conn, par = (synth.hex_mesh if kind == "hex8" else synth.tet10_mesh)(n)
+    u = synth.displacement_modes(X, 1.0 / n, seed=0)
+    p = synth.num_inputs(n_sv)
+    Av = synth.structural_vectors(n_sv)
+    theta = synth.micnn_params(p, h, L, seed=1)
+    grp = synth.reaction_groups(X)
+    R = np.array([0.03, -0.02])
+    Lo, go, ro = calib.residual_loss_and_grad(theta, X, conn, u, grp, R, Av, p, h, L)
+    gm = api.Model(theta, n_sv, h, L, A=Av, normalize=False, algorithm="adjoint")
+    mesh = api.FEMesh(X, conn, colour=par)
+    loss, tb = api.residual_loss_and_grad(gm, mesh, torch.tensor(u, device="cuda"),
+                                          torch.tensor(grp, device="cuda"), R, prec=prec)
+    assert abs(loss.item() - Lo) <= (1e-12 if prec == "fp64" else 1e-5) * abs(Lo)
+    close(tb.cpu().numpy(), go, tol, "theta_bar")
+
+
+def test_residual_loss_cotangent_and_empty_groups():
+    """pa_residual_loss against the definition on a random residual, with and
+    without reaction boundaries."""
+    api = need_gpu()
+    X, _, _ = synth.hex_mesh(4)
+    grp = synth.reaction_groups(X)
+    r = synth.rng(3).normal(size=grp.size)
+    R = np.array([0.5, -1.5])
+    loss, rbar = api.residual_loss(torch.tensor(r, device="cuda"), torch.tensor(grp, device="cuda"), R)
+    L_ref = np.sum(r[grp == -1] ** 2) + sum((R[b] - r[grp == b].sum()) ** 2 for b in range(2))
+    rb_ref = np.where(grp == -1, 2 * r, 0.0)
+    for b in range(2):
+        rb_ref[grp == b] = -2 * (R[b] - r[grp == b].sum())
+    assert abs(loss.item() - L_ref) <= 1e-13 * L_ref
+    close(rbar.cpu().numpy(), rb_ref, 1e-14, "r_bar")
+    free = np.full(grp.size, -1, dtype=np.int32)
+    loss0, rbar0 = api.residual_loss(torch.tensor(r, device="cuda"), torch.tensor(free, device="cuda"), [])
+    assert abs(loss0.item() - np.sum(r ** 2)) <= 1e-13 * np.sum(r ** 2)
+    close(rbar0.cpu().numpy(), 2 * r, 1e-15, "r_bar free")
