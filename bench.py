@@ -185,6 +185,15 @@ def other_workload(args):
             print(f"[bench] {prec}/{algo}: {ms:.3f} ms, {n / (ms / 1e3):.3e} qp/s", file=sys.stderr, flush=True)
             del out
             bufs.clear()
+        for prec in ("fp64", "fp32"):  # the paper's storage: tau (6) and cc (21) per point
+            gm = api.Model(theta, n_sv, h, Lh, A=Av, normalize=True, algorithm="adjoint")
+            bufs = {}
+            def call_v():
+                bufs["out"] = api.energy_stress_tangent_voigt(gm, F, prec=prec)
+            ms, kern = _profiled(lib, call_v, steps, warmup)
+            res[f"{prec}/adjoint/voigt"] = {"ms": ms, "qp_per_s": n / (ms / 1e3), "kernels_ms": kern}
+            print(f"[bench] {prec}/adjoint/voigt: {ms:.3f} ms, {n / (ms / 1e3):.3e} qp/s", file=sys.stderr, flush=True)
+            bufs.clear()
         best = res["fp64/adjoint"]
         line = {"metric": "qp evals/s (Psi+P+tangent) & elements assembled/s, FP64 vs FP32/BF16 at stated error",
                 "value": best["qp_per_s"], "unit": "qp evals/s", "n_gpus": 1, "steps": steps, "warmup": warmup,

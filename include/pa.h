@@ -173,6 +173,18 @@ int pa_energy_stress_tangent(const pa_model_desc* desc, const void* prepared, in
                              double* AA, int32_t* n_bad, void* workspace, size_t ws_bytes,
                              void* stream);
 
+/* Psi, Kirchhoff stress tau and spatial tangent cc at n_qp points, the
+ * paper's own storage of the constitutive update (App. A.1-A.2, the tau and
+ * cc of eqs. stress-cgo and stiffnes-cgo): tau [6][n_qp] and cc [21][n_qp]
+ * in Voigt slots (11, 22, 33, 23, 13, 12), cc as the upper triangle of the
+ * symmetric 6 x 6 matrix, row by row ((0,0), (0,1), ..., (0,5), (1,1), ...).
+ * 216 bytes per point instead of the 720 of P and AA.  psi, tau or cc may be
+ * NULL (cc NULL: no network Hessian is formed).  Same workspace as
+ * pa_energy_stress_tangent. */
+int pa_energy_stress_tangent_voigt(const pa_model_desc* desc, const void* prepared, int prec, int64_t n_qp,
+                                   const double* F, double* psi, double* tau, double* cc, int32_t* n_bad,
+                                   void* workspace, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- elements */
 /* Reference shape gradients and quadrature volumes (eqs. r-quad, k-quad):
  *   X [3][n_nodes] node coordinates, conn [nen][n_el];

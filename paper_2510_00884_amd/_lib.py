@@ -70,6 +70,7 @@ SIGNATURES = {
     "pa_assemble_csr": (C.c_int, [PMESH, PCOL, PCSR, P, P, P, P, I32, P]),
     "pa_tangent_build": (C.c_int, [PDESC, P, C.c_int, PMESH, PCOL, PCSR, P, P, P, P, P, SZ, P]),
     "pa_node_incidence": (C.c_int, [I32, I64, I64, P, P, P]),
+    "pa_energy_stress_tangent_voigt": (C.c_int, [PDESC, P, C.c_int, I64, P, P, P, P, P, P, SZ, P]),
     "pa_residual_loss_workspace": (SZ, [I64, I32]),
     "pa_residual_loss": (C.c_int, [I64, P, P, I32, P, P, P, P, SZ, P]),
     "pa_residual_param_backward_workspace": (SZ, [PDESC, PMESH, C.c_int]),

@@ -142,6 +142,58 @@ def energy_stress_tangent(model: Model, F, prec="fp64", psi=True, P=True, A=True
     return out
 
 
+def energy_stress_tangent_voigt(model: Model, F, prec="fp64", psi=True, tau=True, cc=True, soa=False,
+                                n_bad=None, workspace=None, out=None):
+    """Psi (n,), Kirchhoff tau (6, n) and spatial tangent cc (21, n) in Voigt
+    slots (11, 22, 33, 23, 13, 12); cc holds the upper triangle of the 6 x 6
+    matrix row by row.  ``F`` is (n, 3, 3) or, with soa=True, (9, n)."""
+    Fs = F if soa else _soa9(F)
+    n = Fs.shape[1]
+    dev = Fs.device
+    if out is None:
+        out = {}
+        if psi:
+            out["psi"] = torch.empty(n, dtype=torch.float64, device=dev)
+        if tau:
+            out["tau"] = torch.empty((6, n), dtype=torch.float64, device=dev)
+        if cc:
+            out["cc"] = torch.empty((21, n), dtype=torch.float64, device=dev)
+    ws_bytes = model.lib.pa_material_workspace_bytes(C.byref(model.desc), n)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    L.check(model.lib.pa_energy_stress_tangent_voigt(
+        C.byref(model.desc), _p(model.prepared), _prec(prec), n, _p(Fs), _p(out.get("psi")), _p(out.get("tau")),
+        _p(out.get("cc")), _p(n_bad), _p(workspace), workspace.numel(), _stream()),
+        "pa_energy_stress_tangent_voigt")
+    return out
+
+
+VOIGT = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+
+
+def voigt_unpack(tau, cc):
+    """(6, n), (21, n) Voigt arrays -> tau (n, 3, 3), cc (n, 3, 3, 3, 3) with
+    the minor and major symmetries restored (host helper for callers and
+    tests)."""
+    tau = tau.cpu().numpy() if hasattr(tau, "cpu") else np.asarray(tau)
+    cc = cc.cpu().numpy() if hasattr(cc, "cpu") else np.asarray(cc)
+    n = tau.shape[1]
+    T = np.zeros((n, 3, 3))
+    for a, (i, j) in enumerate(VOIGT):
+        T[:, i, j] = T[:, j, i] = tau[a]
+    Cm = np.zeros((n, 3, 3, 3, 3))
+    t = 0
+    for a in range(6):
+        for b in range(a, 6):
+            (i, j), (k, l) = VOIGT[a], VOIGT[b]
+            for (p_, q_) in {(i, j), (j, i)}:
+                for (r_, s_) in {(k, l), (l, k)}:
+                    Cm[:, p_, q_, r_, s_] = cc[t]
+                    Cm[:, r_, s_, p_, q_] = cc[t]
+            t += 1
+    return T, Cm
+
+
 class FEMesh:
     """Device-resident mesh: geometry, CSR pattern, element->CSR map and a
     colouring.  Elements are renumbered colour by colour (``perm[i]`` is the

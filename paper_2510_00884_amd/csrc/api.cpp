@@ -132,7 +132,8 @@ int check_prec(int prec) {
 
 // F -> (psi, P, AA) through features, network and chain rule.
 int run_material(const pa_model_desc* d, const void* prepared, int prec, int64_t n, const double* F,
-                 double* psi, double* P, double* A, int32_t* n_bad, unsigned char* ws, hipStream_t s) {
+                 double* psi, double* P, double* A, int32_t* n_bad, unsigned char* ws, hipStream_t s,
+                 bool voigt = false) {
   const int p = p_of(d);
   const PrepLayout lay = layout_of(d);
   const ModelConst mc = model_const(d);
@@ -150,7 +151,11 @@ int run_material(const pa_model_desc* d, const void* prepared, int prec, int64_t
   }
   if (rc == -2) return fail(PA_ERR_UNSUPPORTED, "network algorithm %d not available", d->algorithm);
   if (rc) return fail(PA_ERR_ARG, "bad network configuration");
-  {
+  if (voigt) {
+    Prof pr("chain_voigt", s);
+    if (launch_chain_voigt(d->n_sv, n, F, Nout, (const double*)(prep + lay.hdr), mc, psi, P, A, s))
+      return fail(PA_ERR_ARG, "bad n_sv");
+  } else {
     Prof pr("chain", s);
     if (launch_chain(d->n_sv, n, F, Nout, (const double*)(prep + lay.hdr), mc, psi, P, A, n_bad, s))
       return fail(PA_ERR_ARG, "bad n_sv");
@@ -242,6 +247,20 @@ int pa_energy_stress_tangent(const pa_model_desc* d, const void* prepared, int p
   if (!workspace || (int64_t)ws_bytes < material_ws(d, n))
     return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)material_ws(d, n));
   return run_material(d, prepared, prec, n, F, psi, P, A, n_bad, (unsigned char*)workspace, S(stream));
+}
+
+int pa_energy_stress_tangent_voigt(const pa_model_desc* d, const void* prepared, int prec, int64_t n,
+                                   const double* F, double* psi, double* tau, double* cc, int32_t* n_bad,
+                                   void* workspace, size_t ws_bytes, void* stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if ((rc = check_prec(prec))) return rc;
+  if (n < 0) return fail(PA_ERR_ARG, "n_qp < 0");
+  if (n == 0) return PA_OK;
+  if (!prepared || !F) return fail(PA_ERR_ARG, "prepared and F must be non-NULL");
+  if (!workspace || (int64_t)ws_bytes < material_ws(d, n))
+    return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)material_ws(d, n));
+  return run_material(d, prepared, prec, n, F, psi, tau, cc, n_bad, (unsigned char*)workspace, S(stream), true);
 }
 
 int pa_mesh_geometry(int32_t nen, int64_t n_el, int64_t n_nodes, const double* X, const int32_t* conn,

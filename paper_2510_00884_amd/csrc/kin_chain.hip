@@ -100,6 +100,36 @@ __global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restri
   (void)n_bad;
 }
 
+// Psi, Kirchhoff stress tau [6][n] and spatial tangent cc [21][n] in Voigt
+// slots (11, 22, 33, 23, 13, 12), the tangent as the upper triangle of the
+// 6 x 6 matrix in TRI order: the paper's own storage of the constitutive
+// update (App. A.1-A.2), 216 instead of 720 bytes per point.
+template <int NSV>
+__global__ void __launch_bounds__(256) k_chain_voigt(int64_t n, const double* __restrict__ F,
+                                                     const double* __restrict__ Nout, const double* __restrict__ N0,
+                                                     ModelConst mc, double* __restrict__ psi,
+                                                     double* __restrict__ tau, double* __restrict__ cc) {
+  constexpr int P = Feat<NSV>::P;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double f[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = F[i * n + t];
+  Kin k;
+  kin_compute<NSV>(f, mc, k);
+  if (psi) psi[t] = Nout[t] - N0[0];
+  if (!tau && !cc) return;
+  const bool second = cc != nullptr;
+  auto N1 = [&](int m) { return Nout[(int64_t)(1 + m) * n + t]; };
+  auto N2 = [&](int i) { return Nout[(int64_t)(1 + P + i) * n + t]; };
+  double S[6], CCt[21];
+  chain_material_stream<NSV>(k, mc, N1, N2, second, S, CCt);
+  push_spatial(
+      k, S, CCt, second,
+      [&](int c, double v) { if (tau) tau[(int64_t)c * n + t] = v; },
+      [&](int c, double v) { cc[(int64_t)c * n + t] = v; });
+}
+
 // dPsi/dC (6 slots) and d2Psi/dCdC (21 upper-triangle tensor components) per
 // point, SoA [27][n]: the material-form quantities the element kernels
 // integrate.  Fully unrolled: the network derivatives are loaded once and the
@@ -180,6 +210,18 @@ int launch_material_cc(int nsv, int64_t n, const double* F, const double* Nout, 
     case 0: k_material_cc<0><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, mc, SC); break;
     case 1: k_material_cc<1><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, mc, SC); break;
     case 2: k_material_cc<2><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, mc, SC); break;
+    default: return -1;
+  }
+  return 0;
+}
+
+int launch_chain_voigt(int nsv, int64_t n, const double* F, const double* Nout, const double* N0,
+                       const ModelConst& mc, double* psi, double* tau, double* cc, hipStream_t s) {
+  if (n == 0) return 0;
+  switch (nsv) {
+    case 0: k_chain_voigt<0><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, tau, cc); break;
+    case 1: k_chain_voigt<1><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, tau, cc); break;
+    case 2: k_chain_voigt<2><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, tau, cc); break;
     default: return -1;
   }
   return 0;

@@ -420,6 +420,56 @@ __host__ __device__ inline void chain_material_stream(const Kin& k, const ModelC
   }
 }
 
+// Spatial Voigt outputs (App. A.1-A.2): Kirchhoff stress tau = F S F^T and
+// spatial tangent cc_ijkl = F_iI F_jJ F_kK F_lL CC_IJKL with S = 2 S~ and
+// CC = 4 CC~.  In Voigt slots (11, 22, 33, 23, 13, 12) both are products with
+// M[c][b] = sum over the index pairs (K, L) of slot c of F_kK F_lL, (k, l) the
+// pair of slot b:  tau = 2 M^T s~,  cc = 4 M^T CC~ M  (upper triangle, TRI).
+template <class StoreT, class StoreC>
+__host__ __device__ inline void push_spatial(const Kin& k, const double* S, const double* CCt, bool tangent,
+                                             StoreT storeT, StoreC storeC) {
+  const double* F = k.F;
+  double M[6][6];  // M[c][b]
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    int kk, ll;
+    slot_pair(b, kk, ll);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      int K, L;
+      slot_pair(c, K, L);
+      M[c][b] = (K == L) ? F[3 * kk + K] * F[3 * ll + K] : F[3 * kk + K] * F[3 * ll + L] + F[3 * kk + L] * F[3 * ll + K];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) t += M[c][b] * S[c];
+    storeT(b, 2.0 * t);
+  }
+  if (!tangent) return;
+  double X[6][6];  // X = CC~ M
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      double x = 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) x += CCt[TRI(a, c)] * M[c][b];
+      X[a][b] = x;
+    }
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b = a; b < 6; ++b) {
+      double y = 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) y += M[c][a] * X[c][b];
+      storeC(TRI(a, b), 4.0 * y);
+    }
+}
+
 // P = 2 F S~ and AA_iJkL = 2 delta_ik S~_JL + 4 F_iI F_kK CC~_IJKL.
 // Calls sink(index, value) for the 9 stress and 81 tangent components.
 template <class StoreP, class StoreA>

@@ -53,6 +53,8 @@ int launch_features(int nsv, int64_t n, const double* F, const ModelConst& mc, d
                     int32_t* n_bad, hipStream_t s);
 int launch_material_cc(int nsv, int64_t n, const double* F, const double* Nout, const ModelConst& mc,
                        double* SC, hipStream_t s);
+int launch_chain_voigt(int nsv, int64_t n, const double* F, const double* Nout, const double* N0,
+                       const ModelConst& mc, double* psi, double* tau, double* cc, hipStream_t s);
 int launch_chain(int nsv, int64_t n, const double* F, const double* Nout, const double* N0,
                  const ModelConst& mc, double* psi, double* P, double* A, int32_t* n_bad, hipStream_t s);
 

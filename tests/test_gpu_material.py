@@ -158,3 +158,25 @@ def test_adjoint_bf16_unsupported():
     from paper_2510_00884_amd._lib import PaError
     with pytest.raises(PaError):
         api.energy_stress_tangent(gm, F, prec="bf16")
+
+
+@pytest.mark.parametrize("n_sv,h,L,normalize", [(2, 32, 2, True), (1, 64, 3, True), (0, 16, 2, False)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_voigt_spatial_outputs(n_sv, h, L, normalize, prec, tol):
+    """Kirchhoff stress and spatial tangent in Voigt form (pushed forward
+    from S~ and CC~ on the GPU) against the oracle's tau and cc, computed by
+    the paper's push-forward tables."""
+    api = need_gpu()
+    say("voigt", n_sv, h, L, normalize, prec)
+    gm, om = build(api, n_sv, h, L, normalize, algorithm="adjoint")
+    n = 1000
+    F = synth.sample_F(n, seed=4)
+    out = api.energy_stress_tangent_voigt(gm, torch.tensor(F, device="cuda"), prec=prec)
+    tau, cc = api.voigt_unpack(out["tau"], out["cc"])
+    ref = ncm.stress_stiffness(F, om)
+    e = (rel(out["psi"].cpu().numpy(), ref["psi"]), rel(tau, ref["tau"]), rel(cc, ref["cc"]))
+    say("  errors psi/tau/cc", e)
+    assert max(e) < tol
+    # stress only: no tangent, same tau
+    out2 = api.energy_stress_tangent_voigt(gm, torch.tensor(F, device="cuda"), prec=prec, cc=False, psi=False)
+    close(out2["tau"].cpu().numpy(), out["tau"].cpu().numpy(), 1e-14, "tau without tangent")
