@@ -31,6 +31,16 @@ R9  Optional normalisation (energy- and stress-free reference state):
     Psi = N(K) - N(0) - sum_{i<=j} kappa_ij K_{4,ij},
     kappa_ij = dN/dK_{4,ij}(0) + 2 dN/dK_{5,ij}(0).
 R10 J <= 0: the isochoric factors use I3 = J^2 > 0; values are still produced.
+R12 CANN inner network (App. B.1, eq. cann-def) with the layers of the
+    hyper-parameter table: f0 = identity; for every input m four branches,
+    powers {1, 2} times functions {w1 x, exp(w1 x) - 1}, each with its own
+    inner weight w1 and outer weight w2, so 8 parameters per input, ordered
+    per input as (1, lin), (2, lin), (1, exp), (2, exp), each (w1, w2).  The
+    table's count of 33 parameters for three inputs does not follow from the
+    printed layers; that count is unpinned.
+R13 Gent-Thomas (eq. gt) as an inner function of the isotropic features:
+    N = c1 K1 + c2 ((2/3) log(K2 + 3^{3/2}) - log 3) + c3 K3, with
+    (c1, c2, c3) = (0.5, 1, 1) for eq. gt; other features carry no weight.
 """
 from __future__ import annotations
 
@@ -209,6 +219,75 @@ class Model:
     # inner function seen by the chain rule: value, gradient, Hessian in K
     def inner(self, K):
         N, dN, d2N = micnn(K, self.hidden, self.a, self.b)
+        if self.normalize:
+            npair = self.kappa.shape[0]
+            N = N - self.N0 - K[:, 3:3 + npair] @ self.kappa
+            dN = dN.copy()
+            dN[:, 3:3 + npair] -= self.kappa
+        return N, dN, d2N
+
+
+def cann(K, theta):
+    """CANN inner network (eq. cann-def) and its derivatives (eq.
+    cann-chain-rule, diagonal Hessian) under reading R12.  theta: 8 p."""
+    n, p = K.shape
+    th = np.asarray(theta).reshape(p, 4, 2)
+    N = np.zeros(n, dtype=np.result_type(K, th))
+    dN = np.zeros((n, p), dtype=N.dtype)
+    d2N = np.zeros((n, p, p), dtype=N.dtype)
+    for m in range(p):
+        x = K[:, m]
+        for k, (e, kind) in enumerate([(1, 0), (2, 0), (1, 1), (2, 1)]):
+            w1, w2 = th[m, k]
+            f1 = x ** e                        # power layer
+            d1 = e * x ** (e - 1)
+            dd1 = e * (e - 1) * x ** max(e - 2, 0) if e >= 2 else 0.0 * x
+            if kind == 0:                      # f2 = w1 f1
+                f2, d2, dd2 = w1 * f1, w1 + 0.0 * x, 0.0 * x
+            else:                              # f2 = exp(w1 f1) - 1
+                ex = np.exp(w1 * f1)
+                f2, d2, dd2 = ex - 1.0, w1 * ex, w1 * w1 * ex
+            N = N + w2 * f2
+            dN[:, m] += w2 * d2 * d1
+            d2N[:, m, m] += w2 * (dd2 * d1 * d1 + d2 * dd1)
+    return N, dN, d2N
+
+
+def gent_thomas(K, coef):
+    """Gent-Thomas inner function (eq. gt, reading R13)."""
+    c1, c2, c3 = coef
+    u = K[:, 1] + S32
+    N = c1 * K[:, 0] + c2 * ((2.0 / 3.0) * np.log(u) - np.log(3.0)) + c3 * K[:, 2]
+    dN = np.zeros_like(K, dtype=np.result_type(K, u))
+    d2N = np.zeros(K.shape + (K.shape[1],), dtype=dN.dtype)
+    dN[:, 0] = c1
+    dN[:, 1] = c2 * (2.0 / 3.0) / u
+    dN[:, 2] = c3
+    d2N[:, 1, 1] = -c2 * (2.0 / 3.0) / u ** 2
+    return N, dN, d2N
+
+
+class ClosedModel:
+    """An inner function other than the MICNN (CANN or Gent-Thomas) with the
+    same structural vectors and normalisation (R9) as Model."""
+
+    def __init__(self, fn, theta, Avec, normalize=False):
+        self.fn = fn
+        self.theta = theta
+        self.Avec = np.asarray(Avec, dtype=float).reshape(-1, 3)
+        self.normalize = bool(normalize)
+        n_sv = self.Avec.shape[0]
+        self.p = num_inputs(n_sv)
+        self.kappa = np.zeros(len(pairs(n_sv)))
+        self.N0 = 0.0
+        if self.normalize:
+            N0, dN0, _ = fn(np.zeros((1, self.p)), theta)
+            npair = len(pairs(n_sv))
+            self.N0 = float(np.real(N0[0]))
+            self.kappa = np.real(dN0[0, 3:3 + npair] + 2.0 * dN0[0, 3 + npair:3 + 2 * npair])
+
+    def inner(self, K):
+        N, dN, d2N = self.fn(K, self.theta)
         if self.normalize:
             npair = self.kappa.shape[0]
             N = N - self.N0 - K[:, 3:3 + npair] @ self.kappa

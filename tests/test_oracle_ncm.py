@@ -168,19 +168,10 @@ def test_neo_hookean_reduction(n_sv):
 
 
 def test_gent_thomas_inner_function():
-    """Gent-Thomas (eq. gt) through the I2~ feature: Psi = 0.5 K1 +
-    log(((K2 + 3^1.5)^(2/3))/3) + K3; stress and stiffness from the push-forward
-    route against complex-step derivatives of Psi written directly in F."""
-    s32 = 3.0 ** 1.5
-
-    def inner(K):
-        u = K[:, 1] + s32
-        N = 0.5 * K[:, 0] + (2.0 / 3.0) * np.log(u) - np.log(3.0) + K[:, 2]
-        dN = np.zeros_like(K); d2N = np.zeros(K.shape + (K.shape[1],), dtype=K.dtype)
-        dN[:, 0] = 0.5; dN[:, 1] = (2.0 / 3.0) / u; dN[:, 2] = 1.0
-        d2N[:, 1, 1] = -(2.0 / 3.0) / u ** 2
-        return N, dN, d2N
-
+    """Gent-Thomas (eq. gt) through the I2~ feature (reading R13): Psi =
+    0.5 K1 + log(((K2 + 3^1.5)^(2/3))/3) + K3; stress and stiffness from the
+    push-forward route against complex-step derivatives of Psi written
+    directly in F."""
     def psi_F(F):
         J = ncm._det3(F)
         C = np.einsum("nki,nkj->nij", F, F)
@@ -190,13 +181,75 @@ def test_gent_thomas_inner_function():
         I2t = I2 * (J * J) ** (-2.0 / 3.0)
         return 0.5 * (I1t - 3) + np.log(I2t / 3) + (J - 1) ** 2
 
-    m = make_model(0, 4, 2)
+    m = ncm.ClosedModel(ncm.gent_thomas, (0.5, 1.0, 1.0), np.zeros((0, 3)))
     F = rand_F(40, seed=4)
-    out = ncm.stress_stiffness(F, m, inner=inner)
+    out = ncm.stress_stiffness(F, m)
     np.testing.assert_allclose(out["psi"], psi_F(F), rtol=1e-13, atol=1e-14)
     assert rel(out["P"], cs_grad(psi_F, F)) < 1e-12
-    Pfun = lambda X: ncm.stress_stiffness(X, m, inner=inner)["P"]
+    Pfun = lambda X: ncm.stress_stiffness(X, m)["P"]
     assert rel(out["A"], cs_jac(Pfun, F)) < 1e-12
+
+
+def cann_theta(p, seed=3):
+    return np.abs(np.random.default_rng(seed).normal(0.0, 0.3, size=8 * p))
+
+
+@pytest.mark.parametrize("n_sv", [0, 2])
+def test_cann_derivatives_by_complex_step(n_sv):
+    """Gradient and (diagonal) Hessian of the CANN (eq. cann-chain-rule)
+    against complex-step derivatives of its value (eq. cann-def)."""
+    p = ncm.num_inputs(n_sv)
+    th = cann_theta(p)
+    K = np.abs(np.random.default_rng(5).normal(0.0, 0.4, size=(30, p)))
+    N, dN, d2N = ncm.cann(K, th)
+    h = 1e-20
+    for m in range(p):
+        E = np.zeros(p); E[m] = h
+        Nc, dNc, _ = ncm.cann(K + 1j * E, th)
+        assert np.max(np.abs(np.imag(Nc) / h - dN[:, m])) <= 1e-13 * max(1.0, np.abs(dN).max())
+        assert np.max(np.abs(np.imag(dNc) / h - d2N[:, :, m])) <= 1e-13 * max(1.0, np.abs(d2N).max())
+    off = d2N.copy()
+    off[:, np.arange(p), np.arange(p)] = 0.0
+    assert np.all(off == 0.0)
+
+
+def test_cann_neo_hookean_reduction():
+    """A CANN with only the linear power-1 branches of K1 (w1 w2 = mu/2) and
+    K3 (w1 w2 = kappa/2) is the Neo-Hookean energy exactly."""
+    mu, kap = 1.7, 5.3
+    th = np.zeros((3, 4, 2))
+    th[0, 0] = (2.0, mu / 4)
+    th[2, 0] = (0.5, kap)
+    m = ncm.ClosedModel(ncm.cann, th.reshape(-1), np.zeros((0, 3)))
+    F = rand_F(64, seed=2)
+    out = ncm.stress_stiffness(F, m)
+    psi, P, A = nh_closed(F, mu, kap)
+    np.testing.assert_allclose(out["psi"], psi, rtol=1e-13, atol=1e-14)
+    assert rel(out["P"], P) < 1e-13
+    assert rel(out["A"], A) < 1e-13
+
+
+def test_cann_stress_and_tangent_by_complex_step():
+    """P and AA of an orthotropic CANN with the normalised reference state
+    against complex-step derivatives of Psi written in F."""
+    Av = np.eye(3)[:2]
+    p = ncm.num_inputs(2)
+    th = cann_theta(p, seed=8)
+    m = ncm.ClosedModel(ncm.cann, th, Av, normalize=True)
+
+    def psi_F(F):
+        N, _, _ = m.inner(ncm.features(F, Av))
+        return N
+
+    F = rand_F(30, seed=6)
+    out = ncm.stress_stiffness(F, m)
+    np.testing.assert_allclose(out["psi"], psi_F(F), rtol=1e-13, atol=1e-14)
+    assert rel(out["P"], cs_grad(psi_F, F)) < 1e-12
+    Pfun = lambda X: ncm.stress_stiffness(X, m)["P"]
+    assert rel(out["A"], cs_jac(Pfun, F)) < 1e-12
+    I = np.eye(3)[None]
+    ref = ncm.stress_stiffness(I, m)
+    assert abs(ref["psi"][0]) < 1e-14 and np.abs(ref["P"]).max() < 1e-14
 
 
 # ---------------------------------------------------------------- derivative routes
