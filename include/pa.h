@@ -71,6 +71,20 @@ typedef enum {
 
 typedef enum { PA_ACT_SOFTPLUS = 0 } pa_activation;
 
+/* Inner function of the constitutive model.  PA_MODEL_MICNN: the network of
+ * eq. icnn (width, n_hidden, activation, has_bias, algorithm apply).
+ * PA_MODEL_CANN: the CANN of App. B.1 (eq. cann-def) with f0 = identity and,
+ * per input, the branches (power 1, linear), (power 2, linear), (power 1,
+ * exp), (power 2, exp), each with an inner weight w1 and an outer weight w2
+ * (theta: 8 per input, in that order, (w1, w2) per branch; f2 = w1 x or
+ * exp(w1 x) - 1).  PA_MODEL_GENT_THOMAS: eq. (gt) on the isotropic
+ * features, theta = (c1, c2, c3), N = c1 K1 + c2 ((2/3) log(K2 + 3^{3/2}) -
+ * log 3) + c3 K3 ((0.5, 1, 1) is eq. gt).  For the last two, width,
+ * n_hidden, activation, has_bias and algorithm are ignored, the precision
+ * argument is accepted and the arithmetic is FP64, and the parameter
+ * adjoint is not provided. */
+typedef enum { PA_MODEL_MICNN = 0, PA_MODEL_CANN = 1, PA_MODEL_GENT_THOMAS = 2 } pa_model_kind;
+
 /* Description of the neural constitutive model (host struct).
  * Kinematic layer (App. A.2 and App. C):
  *   K = [I1~ - 3, I2~^{3/2} - 3^{3/2}, (J-1)^2,
@@ -95,6 +109,7 @@ typedef struct {
   int32_t normalize;   /* 1: energy- and stress-free reference state        */
   int32_t has_bias;    /* 1: hidden layers carry biases c_k                  */
   int32_t algorithm;   /* pa_algorithm used by the tangent entry points      */
+  int32_t kind;        /* a pa_model_kind value; 0 = MICNN                    */
 } pa_model_desc;
 
 /* Finite-element mesh on the device.  nen/nq: 8/8 (hex8, 2x2x2 Gauss) or

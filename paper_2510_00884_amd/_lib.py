@@ -18,12 +18,14 @@ PA_ACT_SOFTPLUS = 0
 
 PRECISIONS = {"fp64": PA_FP64, "fp32": PA_FP32, "bf16": PA_BF16, "bf16_corr": PA_BF16_CORR}
 ALGORITHMS = {"forward": PA_ALGO_FORWARD, "adjoint": PA_ALGO_ADJOINT}
+PA_MODEL_MICNN, PA_MODEL_CANN, PA_MODEL_GENT_THOMAS = 0, 1, 2
+MODEL_KINDS = {"micnn": PA_MODEL_MICNN, "cann": PA_MODEL_CANN, "gent_thomas": PA_MODEL_GENT_THOMAS}
 
 
 class ModelDesc(C.Structure):
     _fields_ = [("n_sv", C.c_int32), ("A", (C.c_double * 3) * 2), ("n_hidden", C.c_int32),
                 ("width", C.c_int32), ("activation", C.c_int32), ("normalize", C.c_int32),
-                ("has_bias", C.c_int32), ("algorithm", C.c_int32)]
+                ("has_bias", C.c_int32), ("algorithm", C.c_int32), ("kind", C.c_int32)]
 
 
 class Mesh(C.Structure):

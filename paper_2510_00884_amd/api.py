@@ -26,7 +26,7 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _desc(n_sv, width, n_hidden, A=None, normalize=False, has_bias=True, algorithm="forward"):
+def _desc(n_sv, width, n_hidden, A=None, normalize=False, has_bias=True, algorithm="forward", kind="micnn"):
     d = L.ModelDesc()
     d.n_sv = int(n_sv)
     if A is not None:
@@ -40,6 +40,7 @@ def _desc(n_sv, width, n_hidden, A=None, normalize=False, has_bias=True, algorit
     d.normalize = int(bool(normalize))
     d.has_bias = int(bool(has_bias))
     d.algorithm = L.ALGORITHMS[algorithm] if isinstance(algorithm, str) else int(algorithm)
+    d.kind = L.MODEL_KINDS[kind] if isinstance(kind, str) else int(kind)
     return d
 
 
@@ -61,10 +62,12 @@ class Model:
     """A neural constitutive model resident on the GPU (parameters prepared
     once by ``pa_prepare_params``)."""
 
-    def __init__(self, theta, n_sv, width, n_hidden, A=None, normalize=False, has_bias=True,
-                 algorithm="forward", device="cuda"):
+    def __init__(self, theta, n_sv, width=16, n_hidden=2, A=None, normalize=False, has_bias=True,
+                 algorithm="forward", device="cuda", kind="micnn"):
+        """kind: "micnn" (eq. icnn), "cann" (App. B.1) or "gent_thomas" (eq. gt);
+        width and n_hidden apply to the MICNN only."""
         self.lib = L.load()
-        self.desc = _desc(n_sv, width, n_hidden, A, normalize, has_bias, algorithm)
+        self.desc = _desc(n_sv, width, n_hidden, A, normalize, has_bias, algorithm, kind)
         self.n_sv, self.width, self.n_hidden = int(n_sv), int(width), int(n_hidden)
         self.p = self.lib.pa_num_inputs(C.byref(self.desc))
         self.n_params = self.lib.pa_num_params(C.byref(self.desc))

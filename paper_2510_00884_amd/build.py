@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpa.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mlp.hip", "adjoint.hip", "kin_chain.hip", "fe.hip", "api.cpp", "host_setup.cpp"]
+SOURCES = ["mlp.hip", "adjoint.hip", "kin_chain.hip", "fe.hip", "closed.hip", "api.cpp", "host_setup.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", CSRC, "-I", INCLUDE,
           "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

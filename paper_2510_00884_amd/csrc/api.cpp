@@ -87,6 +87,14 @@ inline int npair_of(int n_sv) { return n_sv * (n_sv + 1) / 2; }
 int check_desc(const pa_model_desc* d) {
   if (!d) return fail(PA_ERR_ARG, "desc is NULL");
   if (d->n_sv < 0 || d->n_sv > 2) return fail(PA_ERR_ARG, "n_sv must be 0, 1 or 2 (got %d)", d->n_sv);
+  if (d->kind != PA_MODEL_MICNN && d->kind != PA_MODEL_CANN && d->kind != PA_MODEL_GENT_THOMAS)
+    return fail(PA_ERR_ARG, "unknown model kind %d", d->kind);
+  if (d->kind != PA_MODEL_MICNN) {
+    for (int i = 0; i < d->n_sv; ++i)
+      for (int j = 0; j < 3; ++j)
+        if (!std::isfinite(d->A[i][j])) return fail(PA_ERR_ARG, "structural vector %d is not finite", i);
+    return PA_OK;
+  }
   if (d->n_hidden < 2) return fail(PA_ERR_ARG, "n_hidden must be >= 2 (got %d)", d->n_hidden);
   if (d->width <= 0 || d->width % 16) return fail(PA_ERR_ARG, "width must be a positive multiple of 16 (got %d)", d->width);
   if (d->activation != PA_ACT_SOFTPLUS) return fail(PA_ERR_ARG, "unknown activation %d", d->activation);
@@ -130,35 +138,53 @@ int check_prec(int prec) {
   return PA_OK;
 }
 
+// Header of the prepared buffer (N(0) and the reference-state constants).
+const double* hdr_of(const pa_model_desc* d, const void* prepared) {
+  const unsigned char* prep = (const unsigned char*)prepared;
+  if (d->kind != PA_MODEL_MICNN) return (const double*)(prep + closed_layout(d->kind, p_of(d)).hdr);
+  return (const double*)(prep + layout_of(d).hdr);
+}
+
+// The inner function's value, gradient and (hess) Hessian at n points.
+int run_inner(const pa_model_desc* d, const void* prepared, int prec, int64_t n, const double* K, double* Nout,
+              int hess, hipStream_t s) {
+  int rc;
+  if (d->kind != PA_MODEL_MICNN) {
+    Prof pr("inner_closed", s);
+    rc = launch_inner_closed(d->kind, p_of(d), (const unsigned char*)prepared, npair_of(d->n_sv), n, K, Nout, hess, s);
+    if (rc) return fail(PA_ERR_ARG, "bad inner-function configuration");
+    return PA_OK;
+  }
+  {
+    Prof pr(d->algorithm == PA_ALGO_ADJOINT ? "mlp_adjoint" : "mlp_forward", s);
+    rc = launch_mlp(layout_of(d), prec, d->algorithm, (const unsigned char*)prepared, n, K, Nout, hess, s);
+  }
+  if (rc == -2) return fail(PA_ERR_UNSUPPORTED, "network algorithm %d not available", d->algorithm);
+  if (rc) return fail(PA_ERR_ARG, "bad network configuration");
+  return PA_OK;
+}
+
 // F -> (psi, P, AA) through features, network and chain rule.
 int run_material(const pa_model_desc* d, const void* prepared, int prec, int64_t n, const double* F,
                  double* psi, double* P, double* A, int32_t* n_bad, unsigned char* ws, hipStream_t s,
                  bool voigt = false) {
   const int p = p_of(d);
-  const PrepLayout lay = layout_of(d);
   const ModelConst mc = model_const(d);
   double* K = (double*)ws;
   double* Nout = (double*)(ws + al(8 * (int64_t)p * n));
-  const unsigned char* prep = (const unsigned char*)prepared;
   {
     Prof pr("features", s);
     if (launch_features(d->n_sv, n, F, mc, K, n_bad, s)) return fail(PA_ERR_ARG, "bad n_sv");
   }
-  int rc;
-  {
-    Prof pr(d->algorithm == PA_ALGO_ADJOINT ? "mlp_adjoint" : "mlp_forward", s);
-    rc = launch_mlp(lay, prec, d->algorithm, prep, n, K, Nout, A != nullptr, s);
-  }
-  if (rc == -2) return fail(PA_ERR_UNSUPPORTED, "network algorithm %d not available", d->algorithm);
-  if (rc) return fail(PA_ERR_ARG, "bad network configuration");
+  int rc = run_inner(d, prepared, prec, n, K, Nout, A != nullptr, s);
+  if (rc) return rc;
+  const double* hdr = hdr_of(d, prepared);
   if (voigt) {
     Prof pr("chain_voigt", s);
-    if (launch_chain_voigt(d->n_sv, n, F, Nout, (const double*)(prep + lay.hdr), mc, psi, P, A, s))
-      return fail(PA_ERR_ARG, "bad n_sv");
+    if (launch_chain_voigt(d->n_sv, n, F, Nout, hdr, mc, psi, P, A, s)) return fail(PA_ERR_ARG, "bad n_sv");
   } else {
     Prof pr("chain", s);
-    if (launch_chain(d->n_sv, n, F, Nout, (const double*)(prep + lay.hdr), mc, psi, P, A, n_bad, s))
-      return fail(PA_ERR_ARG, "bad n_sv");
+    if (launch_chain(d->n_sv, n, F, Nout, hdr, mc, psi, P, A, n_bad, s)) return fail(PA_ERR_ARG, "bad n_sv");
   }
   return hip_check("material kernels");
 }
@@ -198,7 +224,9 @@ int32_t pa_num_inputs(const pa_model_desc* d) {
 }
 
 int64_t pa_num_params(const pa_model_desc* d) {
-  if (!d || d->n_sv < 0 || d->n_sv > 2 || d->width <= 0 || d->n_hidden < 1) return -1;
+  if (!d || d->n_sv < 0 || d->n_sv > 2) return -1;
+  if (d->kind == PA_MODEL_CANN || d->kind == PA_MODEL_GENT_THOMAS) return closed_num_params(d->kind, p_of(d));
+  if (d->width <= 0 || d->n_hidden < 1) return -1;
   return theta_layout(d->width, d->n_hidden, p_of(d), d->has_bias ? 1 : 0).total;
 }
 
@@ -206,6 +234,7 @@ int32_t pa_supported(const pa_model_desc* d) { return check_desc(d) == PA_OK ? 1
 
 size_t pa_prepared_bytes(const pa_model_desc* d) {
   if (check_desc(d) != PA_OK) return 0;
+  if (d->kind != PA_MODEL_MICNN) return (size_t)closed_layout(d->kind, p_of(d)).total;
   return (size_t)layout_of(d).total;
 }
 
@@ -213,6 +242,12 @@ int pa_prepare_params(const pa_model_desc* d, const double* theta, void* prepare
   int rc = check_desc(d);
   if (rc) return rc;
   if (!theta || !prepared) return fail(PA_ERR_ARG, "theta and prepared must be non-NULL");
+  if (d->kind != PA_MODEL_MICNN) {
+    if (launch_prepare_closed(d->kind, p_of(d), closed_num_params(d->kind, p_of(d)), theta, (unsigned char*)prepared,
+                              d->normalize ? 1 : 0, npair_of(d->n_sv), S(stream)))
+      return fail(PA_ERR_UNSUPPORTED, "prepare failed");
+    return hip_check("pa_prepare_params");
+  }
   const PrepLayout lay = layout_of(d);
   const ThetaLayout tl = theta_layout(d->width, d->n_hidden, p_of(d), d->has_bias ? 1 : 0);
   rc = launch_prepare(lay, tl, theta, (unsigned char*)prepared, d->normalize ? 1 : 0, npair_of(d->n_sv), S(stream));
@@ -293,7 +328,6 @@ int element_front(const pa_model_desc* d, const void* prepared, int prec, const 
   unsigned char* mws = ws + al(8 * 9 * n) + al(8 * 27 * n);
   double* K = (double*)mws;
   double* Nout = (double*)(mws + al(8 * (int64_t)p * n));
-  const PrepLayout lay = layout_of(d);
   const ModelConst mc = model_const(d);
   {
     Prof pr("gather_F", s);
@@ -303,13 +337,8 @@ int element_front(const pa_model_desc* d, const void* prepared, int prec, const 
     Prof pr("features", s);
     launch_features(d->n_sv, n, F, mc, K, n_bad, s);
   }
-  int rc;
-  {
-    Prof pr(d->algorithm == PA_ALGO_ADJOINT ? "mlp_adjoint" : "mlp_forward", s);
-    rc = launch_mlp(lay, prec, d->algorithm, (const unsigned char*)prepared, n, K, Nout, 1, s);
-  }
-  if (rc == -2) return fail(PA_ERR_UNSUPPORTED, "network algorithm %d not available", d->algorithm);
-  if (rc) return fail(PA_ERR_ARG, "bad network configuration");
+  int rc = run_inner(d, prepared, prec, n, K, Nout, 1, s);
+  if (rc) return rc;
   {
     Prof pr("material_cc", s);
     launch_material_cc(d->n_sv, n, F, Nout, mc, SC, s);
@@ -465,6 +494,7 @@ int pa_residual_param_backward(const pa_model_desc* d, const void* prepared, int
                                size_t ws_bytes, void* stream) {
   int rc = check_desc(d);
   if (rc) return rc;
+  if (d->kind != PA_MODEL_MICNN) return fail(PA_ERR_UNSUPPORTED, "the parameter adjoint is provided for the MICNN");
   if (prec != PA_FP64 && prec != PA_FP32) return fail(PA_ERR_UNSUPPORTED, "supports PA_FP64 and PA_FP32");
   if (d->normalize) return fail(PA_ERR_UNSUPPORTED, "differentiates the raw network (normalize = 0)");
   if ((rc = check_mesh(m))) return rc;
@@ -572,6 +602,7 @@ int pa_param_backward(const pa_model_desc* d, const void* prepared, int prec, in
                       const double* P_bar, double* theta_bar, void* workspace, size_t ws_bytes, void* stream) {
   int rc = check_desc(d);
   if (rc) return rc;
+  if (d->kind != PA_MODEL_MICNN) return fail(PA_ERR_UNSUPPORTED, "the parameter adjoint is provided for the MICNN");
   if (prec != PA_FP64 && prec != PA_FP32) return fail(PA_ERR_UNSUPPORTED, "pa_param_backward supports PA_FP64 and PA_FP32");
   if (d->normalize) return fail(PA_ERR_UNSUPPORTED, "pa_param_backward differentiates the raw network (normalize = 0)");
   if (n < 0) return fail(PA_ERR_ARG, "n_qp < 0");

@@ -44,6 +44,24 @@ struct ThetaLayout {
 };
 
 PrepLayout prep_layout(int H, int L, int P);
+
+// Inner functions other than the MICNN (closed.hip); values match pa_model_kind.
+enum { MODEL_MICNN = 0, MODEL_CANN = 1, MODEL_GENT_THOMAS = 2 };
+struct ClosedLayout {
+  int64_t hdr, theta, total;  // header (N(0), kappa), parameters
+};
+inline int closed_num_params(int kind, int p) { return kind == MODEL_CANN ? 8 * p : 3; }
+inline ClosedLayout closed_layout(int kind, int p) {
+  ClosedLayout c{};
+  c.hdr = 0;
+  c.theta = 256;
+  c.total = 256 + ((8 * (int64_t)closed_num_params(kind, p) + 255) & ~int64_t(255));
+  return c;
+}
+int launch_prepare_closed(int kind, int p, int n_params, const double* theta, unsigned char* prep, int normalize,
+                          int npair, hipStream_t s);
+int launch_inner_closed(int kind, int p, const unsigned char* prep, int npair, int64_t n, const double* K,
+                        double* out, int hess, hipStream_t s);
 ThetaLayout theta_layout(int H, int L, int P, int has_bias);
 
 // kinematics / chain (kin_chain.hip)

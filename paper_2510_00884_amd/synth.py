@@ -256,3 +256,12 @@ def reaction_groups(X: np.ndarray, tol: float = 1e-12):
     grp[x0, 0] = 0
     grp[np.abs(X[:, 0]) < tol, :] = -2
     return grp.reshape(-1)
+
+
+def cann_params(p: int, seed: int = 1, sigma: float = 0.3) -> np.ndarray:
+    """CANN weights (8 per input: (w1, w2) for the branches (power 1, linear),
+    (power 2, linear), (power 1, exp), (power 2, exp)), all ~ |N(0, sigma)|."""
+    return np.abs(rng(seed).normal(0.0, sigma, size=8 * p))
+
+
+GENT_THOMAS = np.array([0.5, 1.0, 1.0])  # coefficients of eq. (gt)

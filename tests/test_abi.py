@@ -144,3 +144,24 @@ def test_node_incidence(lib, kind, n):
     bad[0, 0] = -1
     assert lib.pa_node_incidence(nen, n_el, X.shape[0], bad.ctypes.data_as(C.c_void_p),
                                  ptr.ctypes.data_as(C.c_void_p), None) == L.PA_ERR_ARG
+
+
+def test_model_kinds_sizes_and_errors(lib):
+    """CANN: 8 parameters per input; Gent-Thomas: 3; unknown kinds rejected;
+    the parameter adjoint refuses non-MICNN kinds before any launch."""
+    for n_sv, p in [(0, 3), (1, 5), (2, 9)]:
+        d = L.ModelDesc()
+        d.n_sv = n_sv
+        d.kind = L.PA_MODEL_CANN
+        assert lib.pa_num_params(C.byref(d)) == 8 * p
+        assert lib.pa_supported(C.byref(d)) == 1
+        assert lib.pa_prepared_bytes(C.byref(d)) >= 8 * (8 * p)
+        d.kind = L.PA_MODEL_GENT_THOMAS
+        assert lib.pa_num_params(C.byref(d)) == 3
+        assert lib.pa_supported(C.byref(d)) == 1
+    d.kind = 7
+    assert lib.pa_supported(C.byref(d)) == 0
+    d.kind = L.PA_MODEL_CANN
+    dummy = C.c_void_p(1)
+    rc = lib.pa_param_backward(C.byref(d), dummy, L.PA_FP64, 0, None, None, dummy, dummy, 1 << 20, None)
+    assert rc == L.PA_ERR_UNSUPPORTED

@@ -129,3 +129,25 @@ def test_tangent_build_adjoint_hessian(kind, n, n_sv, h, L):
         rf, vf = api.tangent_build(gm, mesh, torch.tensor(u, device="cuda"), prec="fp64", assembly=assembly)
         close(rf.cpu().numpy(), rg, 1e-12, f"r ({assembly})")
         close(vf.cpu().numpy(), Kg.data, 1e-12, f"vals ({assembly})")
+
+
+def test_tangent_build_cann():
+    """Tangent build of a hex8 mesh with the CANN inner function."""
+    api = need_gpu()
+    say("tangent_build cann")
+    n, n_sv = 3, 2
+    X, conn, par = synth.hex_mesh(n)
+    u = synth.displacement_modes(X, 1.0 / n, seed=0)
+    p = synth.num_inputs(n_sv)
+    Av = synth.structural_vectors(n_sv)
+    theta = synth.cann_params(p, seed=2)
+    gm = api.Model(theta, n_sv, A=Av, normalize=True, kind="cann")
+    om = ncm.ClosedModel(ncm.cann, theta, Av, normalize=True)
+    mesh = api.FEMesh(X, conn, colour=par)
+    cperm = conn[mesh.perm]
+    dNdX, w, _ = fe.geometry(X, cperm)
+    r_ref, K_ref, _ = fe.element_residual_stiffness(u, cperm, dNdX, w, om)
+    rg, Kg = fe.assemble(cperm, r_ref, K_ref, X.shape[0])
+    rf, vf = api.tangent_build(gm, mesh, torch.tensor(u, device="cuda"), prec="fp64")
+    close(rf.cpu().numpy(), rg, 1e-12, "r")
+    close(vf.cpu().numpy(), Kg.data, 1e-12, "vals")

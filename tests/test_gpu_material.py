@@ -180,3 +180,31 @@ def test_voigt_spatial_outputs(n_sv, h, L, normalize, prec, tol):
     # stress only: no tangent, same tau
     out2 = api.energy_stress_tangent_voigt(gm, torch.tensor(F, device="cuda"), prec=prec, cc=False, psi=False)
     close(out2["tau"].cpu().numpy(), out["tau"].cpu().numpy(), 1e-14, "tau without tangent")
+
+
+@pytest.mark.parametrize("kind", ["cann", "gent_thomas"])
+@pytest.mark.parametrize("n_sv,normalize", [(0, False), (1, True), (2, True)])
+def test_closed_inner_functions(kind, n_sv, normalize):
+    """CANN (App. B.1) and Gent-Thomas (eq. gt) through the same chain rule:
+    Psi, P and AA, and the Voigt outputs, against the oracle."""
+    api = need_gpu()
+    say("closed", kind, n_sv, normalize)
+    p = synth.num_inputs(n_sv)
+    Av = synth.structural_vectors(n_sv)
+    theta = synth.cann_params(p, seed=2) if kind == "cann" else synth.GENT_THOMAS
+    fn = ncm.cann if kind == "cann" else ncm.gent_thomas
+    om = ncm.ClosedModel(fn, theta, Av, normalize=normalize)
+    gm = api.Model(theta, n_sv, A=Av, normalize=normalize, kind=kind)
+    n = 777
+    F = synth.sample_F(n, seed=9)
+    Ft = torch.tensor(F, device="cuda")
+    out = api.energy_stress_tangent(gm, Ft, prec="fp64")
+    psi, P, A = unpack(out, n)
+    ref = ncm.stress_stiffness(F, om)
+    close(psi, ref["psi"] - om.N0 * 0.0, 1e-12, "psi")
+    close(P, ref["P"], 1e-12, "P")
+    close(A, ref["A"], 1e-12, "A")
+    vo = api.energy_stress_tangent_voigt(gm, Ft, prec="fp32")  # no network contraction: FP64 arithmetic
+    tau, cc = api.voigt_unpack(vo["tau"], vo["cc"])
+    close(tau, ref["tau"], 1e-12, "tau")
+    close(cc, ref["cc"], 1e-12, "cc")
