@@ -223,6 +223,35 @@ def other_workload(args):
                 "data": "synthetic",
                 "config": {"workload": "2^20-point stress calibration, MICNN 3x64 softplus, FP32 network"},
                 "precisions": res}
+    elif args.workload == "model_sweep":
+        # the model-size study of App. E: constitutive update (Psi, P, AA) on
+        # 2^20 points for every network size the kernels provide, and the
+        # CANN and Gent-Thomas inner functions
+        n = 1 << 20
+        F = torch.tensor(synth.sample_F(n, seed=0), device="cuda")
+        res = {}
+        cases = [("micnn", w_, l_) for l_ in (2, 3) for w_ in (16, 32, 64)] + [("cann", 0, 0), ("gent_thomas", 0, 0)]
+        for kind, w_, l_ in cases:
+            if kind == "micnn":
+                th = synth.micnn_params(p, w_, l_, seed=1)
+                gm = api.Model(th, n_sv, w_, l_, A=Av, normalize=True, algorithm="adjoint")
+                tag = f"micnn {l_}x{w_}"
+            else:
+                th = synth.cann_params(p, seed=2) if kind == "cann" else synth.GENT_THOMAS
+                gm = api.Model(th, n_sv, A=Av, normalize=True, kind=kind)
+                tag = kind
+            for prec in ("fp64", "fp32"):
+                ms, kern = _profiled(lib, lambda: api.energy_stress_tangent(gm, F, prec=prec), steps, warmup)
+                res[f"{tag}/{prec}"] = {"params": gm.n_params, "ms": ms, "qp_per_s": n / (ms / 1e3),
+                                        "kernels_ms": kern}
+                print(f"[bench] {tag} ({gm.n_params} params) {prec}: {ms:.3f} ms", file=sys.stderr, flush=True)
+        best = res["micnn 2x32/fp64"]
+        line = {"metric": "qp evals/s (Psi+P+tangent) & elements assembled/s, FP64 vs FP32/BF16 at stated error",
+                "value": best["qp_per_s"], "unit": "qp evals/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+                "ms_per_step": best["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f64", "data": "synthetic",
+                "config": {"workload": "model-size sweep: 2^20 independent points, orthotropic (9 inputs)"},
+                "models": res}
     else:  # tet10_56
         n = 56
         X, conn, par = synth.tet10_mesh(n)
@@ -261,7 +290,7 @@ def main():
     ap.add_argument("--variants", default="fp32,bf16,bf16_corr",
                     help="other precisions timed after the headline run ('' for none)")
     ap.add_argument("--workload", default="hex8_64",
-                    choices=["hex8_64", "points_2pow22", "calib_2pow20", "tet10_56"],
+                    choices=["hex8_64", "points_2pow22", "calib_2pow20", "tet10_56", "model_sweep"],
                     help="hex8_64 (default): the tangent-build bench line; the others measure the point-batch "
                          "precision ladder, the calibration step and the large tet10 mesh")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
