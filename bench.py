@@ -76,10 +76,15 @@ def kernel_bytes_total(name, mesh, p):
     """Algorithmic HBM bytes of one step for a bandwidth-bound kernel."""
     if name == "gather_assemble":
         nd = 3 * mesh.nen
-        return mesh.n_el * (8 * nd * nd + 8 * nd + 4 * mesh.nen * mesh.nen + 4 * mesh.nen) \
+        return mesh.n_el * (72 * sym_blocks(mesh.nen) + 8 * nd + 4 * mesh.nen * mesh.nen + 4 * mesh.nen) \
             + 8 * mesh.nnz + 8 * 3 * mesh.n_nodes + 8 * (3 * mesh.n_nodes + 1) + 8 * (mesh.n_nodes + 1)
     b = kernel_bytes(name, mesh.nen, mesh.nq, p)
     return None if b is None else b * mesh.n_el
+
+
+def sym_blocks(nen):
+    """Distinct 3 x 3 node blocks of a symmetric element tangent."""
+    return nen * (nen + 1) // 2
 
 
 def kernel_bytes(name, nen, nq, p):
@@ -94,8 +99,10 @@ def kernel_bytes(name, nen, nq, p):
     if name == "material_cc":
         return nq * (72 + 8 * (nout - 1) + 8 * 27)              # F, network derivatives in; S~, CC~ out
     inputs = nq * (72 + 8 * 27 + 8) + nq * nen * 3 * 8           # F, S~ and CC~, w, dN/dX
-    if name in ("integrate", "integrate_elmajor"):
+    if name == "integrate":
         return inputs + 8 * nd * nd + 8 * nd                     # K_e, r_e written
+    if name == "integrate_elmajor":
+        return inputs + 72 * sym_blocks(nen) + 8 * nd            # symmetric K_e, r_e written
     if name == "integrate_scatter":
         return inputs + 16 * nd * nd + 16 * nd + 4 * nen * nen   # CSR and r read-modify-write, CSR map
     if name == "assemble":
@@ -405,8 +412,10 @@ def main():
         if dom.startswith("mlp"):
             fl = mlp_flops(dom, h, Lh, p) * n_qp
             ach = fl / per_launch_s
-            sym = "k_mlp_adj<{}, {}, {}, {}, true>".format(h, Lh, p, {"fp64": 0, "fp32": 1}.get(args.prec, -1)) \
-                if dom == "mlp_adjoint" else None
+            pr = {"fp64": 0, "fp32": 1}.get(args.prec, -1)
+            # two-layer networks up to width 32 run the single-wave kernel
+            sym = None if dom != "mlp_adjoint" else (
+                f"k_mlp_adj2<{h}, {p}, {pr}, true>" if Lh == 2 and h <= 32 else f"k_mlp_adj<{h}, {Lh}, {p}, {pr}, true>")
             roof = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[args.prec] / 1e12, "unit": "TFLOP/s",
                     "frac": ach / PEAK[args.prec], "traffic": measured_traffic(sym) if sym else None, "kernel": dom,
                     "algorithmic_per_launch": f"{mlp_flops(dom, h, Lh, p)} FLOP/point x {n_qp} points"}

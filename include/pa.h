@@ -268,7 +268,8 @@ int pa_tangent_build(const pa_model_desc* desc, const void* prepared, int prec, 
 int pa_node_incidence(int32_t nen, int64_t n_el, int64_t n_nodes, const int32_t* conn_host,
                       int64_t* ptr, int32_t* ent);
 /* Workspace of pa_tangent_build_gather: pa_element_workspace_bytes plus the
- * element-major tables r_e [n_el][nd] and K_e [n_el][nd][nd]. */
+ * element-major tables r_e [n_el][nd] and the symmetric K_e, nen (nen + 1) / 2
+ * distinct 3 x 3 node blocks per element ([n_el][nen (nen + 1) / 2][3][3]). */
 size_t pa_gather_workspace_bytes(const pa_model_desc* desc, const pa_mesh* mesh);
 /* One Newton tangent build with node-centric assembly (same result as
  * pa_tangent_build up to summation order): elements are integrated in one

@@ -412,8 +412,8 @@ int pa_tangent_build(const pa_model_desc* d, const void* prepared, int prec, con
 size_t pa_gather_workspace_bytes(const pa_model_desc* d, const pa_mesh* m) {
   const size_t base = pa_element_workspace_bytes(d, m);
   if (!base) return 0;
-  const int64_t nd = 3 * (int64_t)m->nen;
-  return (size_t)(al((int64_t)base) + al(8 * nd * m->n_el) + al(8 * nd * nd * m->n_el));
+  const int64_t nd = 3 * (int64_t)m->nen, nsym = 9 * (int64_t)m->nen * (m->nen + 1) / 2;
+  return (size_t)(al((int64_t)base) + al(8 * nd * m->n_el) + al(8 * nsym * m->n_el));
 }
 
 int pa_tangent_build_gather(const pa_model_desc* d, const void* prepared, int prec, const pa_mesh* m,

@@ -250,11 +250,45 @@ __global__ void __launch_bounds__(256) k_loss_rbar(int64_t n_rows, const double*
 // MODE 0 (tables) writes r_e [nd][n_el] and K_e [nd][nd][n_el]; MODE 1
 // (scatter) adds the rows straight into the global r and CSR values (one
 // launch per colour, so no two threads touch the same entry); MODE 2
-// (element-major tables) writes r_e [n_el][nd] and K_e [n_el][nd][nd], the
-// layout read by the gather assembly.
+// (element-major tables) writes r_e [n_el][nd] and the symmetric K_e
+// [n_el][sym_blocks][3][3], the layout read by the gather assembly.
 template <int NEN>
 __host__ __device__ constexpr int integrate_threads() { return 8 * 3 * NEN; }
 
+// Packed index of entry (al, be) of a symmetric 9 x 9 matrix (upper triangle,
+// row-major; 45 entries).
+__host__ __device__ constexpr int SYM9(int al, int be) {
+  return (al <= be) ? (al * 9 - al * (al - 1) / 2 + (be - al)) : (be * 9 - be * (be - 1) / 2 + (al - be));
+}
+
+template <int V>
+struct Int {
+  static constexpr int value = V;
+};
+
+// Symmetric element tangent in node blocks.  K_e is symmetric (AA has major
+// symmetry), so of its NEN^2 3 x 3 node blocks only NEN (NEN + 1) / 2 are
+// distinct.  Block (a, b) is owned by node a when d = (b - a) mod NEN is
+// below NEN / 2, or equals NEN / 2 and a < NEN / 2 (NEN is even); every
+// unordered pair has exactly one owner and each node owns NEN / 2 or
+// NEN / 2 + 1 blocks.  The owned block (a, d) sits in slot
+// sym_slot(a, d) of the element's table, stored row-major with rows of node a.
+template <int NEN>
+__host__ __device__ constexpr int sym_slot(int a, int d) {
+  return d < NEN / 2 ? a * (NEN / 2) + d : NEN * (NEN / 2) + a;
+}
+template <int NEN>
+__host__ __device__ constexpr int sym_blocks() { return NEN * (NEN + 1) / 2; }
+
+// Two phases per block of E elements.  Phase A: one thread per (point, row
+// i) pushes S~ and CC~ forward to w P_iJ and w AA_iJkL (AA_iJkL = 2 delta_ik
+// S~_JL + 4 F_iI F_kK CC~_IJKL, App. A.1) into LDS.  AA has major symmetry
+// (AA_iJkL = AA_kLiJ), so when the row index of phase B is uniform over a
+// wavefront (E * NEN a multiple of 64) only its 45 distinct entries are
+// stored, which is what lets four blocks share a compute unit's LDS; the
+// wave then runs a copy of the point loop specialised for its row, so every
+// LDS offset is an immediate.  Phase B: one thread per (row i, node a,
+// element) accumulates row 3a + i of K_e and r_e over the points.
 template <int NEN, int MODE>
 __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
     int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* __restrict__ conn,
@@ -268,11 +302,19 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
   constexpr int NT = integrate_threads<NEN>();
   constexpr int NPT = E * NQ;      // points per block
   constexpr int NG = E * NEN * 3;  // shape-gradient values per point slice
+  constexpr bool SYMA = (E * NEN) % 64 == 0;
+  constexpr int NA = SYMA ? 45 : 81;
   static_assert(NG == NT, "one shape-gradient value per thread per point");
   static_assert(3 * NPT <= NT, "one (point, row) pair per thread in phase A");
-  __shared__ double sA[3][3][9][NPT];  // w AA_iJ(kL)
-  __shared__ double sP[3][3][NPT];     // w P_iJ
-  __shared__ double sG[NQ][NEN][3][E];
+  // MODE 2 reuses the block's LDS to stage its tables on the way out
+  constexpr int NS = 9 * sym_blocks<NEN>();  // symmetric tangent values per element
+  constexpr int SP = NS + 1;                 // odd stride between staged elements spreads the LDS banks
+  constexpr int LA = NA * NPT, LP = 9 * NPT, LG = NQ * NEN * 3 * E;
+  constexpr int LST = MODE == 2 ? E * (SP + ND) : 0;
+  __shared__ double lds[LA + LP + LG > LST ? LA + LP + LG : LST];
+  double* sA = lds;       // w AA: [SYM9(3i+J, 3k+L)][t] or [3i+J][3k+L][t]
+  double* sP = lds + LA;  // w P_iJ: [3i+J][t]
+  double(*sG)[NEN][3][E] = reinterpret_cast<double(*)[NEN][3][E]>(lds + LA + LP);
   const int tid = threadIdx.x;
   const int64_t eb = e_begin + xcd_swizzle(blockIdx.x, gridDim.x) * E;
   const int64_t e_end = e_begin + e_count;
@@ -314,7 +356,7 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
     for (int I = 0; I < 3; ++I) Fi[I] = (i == 0) ? Fm[I] : (i == 1) ? Fm[3 + I] : Fm[6 + I];
 #pragma unroll
     for (int J = 0; J < 3; ++J) {
-      sP[i][J][t] = wq * 2.0 * (Fi[0] * S[VI(0, J)] + Fi[1] * S[VI(1, J)] + Fi[2] * S[VI(2, J)]);
+      sP[(3 * i + J) * NPT + t] = wq * 2.0 * (Fi[0] * S[VI(0, J)] + Fi[1] * S[VI(1, J)] + Fi[2] * S[VI(2, J)]);
       // Y_KL = sum_I F_iI CC~_IJKL
       double Y[3][3];
 #pragma unroll
@@ -329,7 +371,12 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
         for (int L = 0; L < 3; ++L) {
           double v = 4.0 * (Fm[3 * k] * Y[0][L] + Fm[3 * k + 1] * Y[1][L] + Fm[3 * k + 2] * Y[2][L]);
           if (k == i) v += 2.0 * S[VI(J, L)];
-          sA[i][J][3 * k + L][t] = wq * v;
+          const int al = 3 * i + J, be = 3 * k + L;
+          if constexpr (SYMA) {
+            if (al <= be) sA[SYM9(al, be) * NPT + t] = wq * v;
+          } else {
+            sA[(al * 9 + be) * NPT + t] = wq * v;
+          }
         }
     }
   }
@@ -341,27 +388,87 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
   const int le = tid % E, a = (tid / E) % NEN, i = tid / (E * NEN);
   const int rho = 3 * a + i;
   const int64_t e = eb + le;
-  double acc[ND];
+  // MODE 2 accumulates row i of the blocks node a owns (sym_slot), the
+  // others full rows of K_e
+  constexpr int HN = NEN / 2;
+  constexpr int NACC = MODE == 2 ? 3 * (HN + 1) : ND;
+  double acc[NACC];
 #pragma unroll
-  for (int c = 0; c < ND; ++c) acc[c] = 0.0;
+  for (int c = 0; c < NACC; ++c) acc[c] = 0.0;
   double rr = 0.0;
+  // IC::value >= 0: the row is that constant; otherwise it is i
+  auto points = [&](auto ic) {
+    constexpr int IC = decltype(ic)::value;
+    const int ii = IC >= 0 ? IC : i;
 #pragma unroll 1
-  for (int q = 0; q < NQ; ++q) {
-    const int buf = q;
-    const int lq = q * E + le;
-    double ga[3];
+    for (int q = 0; q < NQ; ++q) {
+      const int lq = q * E + le;
+      double ga[3];
 #pragma unroll
-    for (int J = 0; J < 3; ++J) ga[J] = sG[buf][a][J][le];
-    rr += sP[i][0][lq] * ga[0] + sP[i][1][lq] * ga[1] + sP[i][2][lq] * ga[2];
-    double T[9];  // T_kL = w AA_iJkL G^a_J
+      for (int J = 0; J < 3; ++J) ga[J] = sG[q][a][J][le];
+      rr += sP[(3 * ii) * NPT + lq] * ga[0] + sP[(3 * ii + 1) * NPT + lq] * ga[1] + sP[(3 * ii + 2) * NPT + lq] * ga[2];
+      double T[9];  // T_kL = w AA_iJkL G^a_J
 #pragma unroll
-    for (int c = 0; c < 9; ++c) T[c] = sA[i][0][c][lq] * ga[0] + sA[i][1][c][lq] * ga[1] + sA[i][2][c][lq] * ga[2];
+      for (int c = 0; c < 9; ++c) {
+        double x = 0.0;
 #pragma unroll
-    for (int b = 0; b < NEN; ++b) {
-      const double h0 = sG[buf][b][0][le], h1 = sG[buf][b][1][le], h2 = sG[buf][b][2][le];
+        for (int J = 0; J < 3; ++J) {
+          const int idx = (IC >= 0) ? SYM9(3 * IC + J, c) : (3 * ii + J) * 9 + c;
+          x += sA[idx * NPT + lq] * ga[J];
+        }
+        T[c] = x;
+      }
+      if constexpr (MODE == 2) {
 #pragma unroll
-      for (int kk = 0; kk < 3; ++kk) acc[3 * b + kk] += T[3 * kk] * h0 + T[3 * kk + 1] * h1 + T[3 * kk + 2] * h2;
+        for (int d = 0; d <= HN; ++d) {
+          const int b = a + d < NEN ? a + d : a + d - NEN;
+          const double h0 = sG[q][b][0][le], h1 = sG[q][b][1][le], h2 = sG[q][b][2][le];
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk) acc[3 * d + kk] += T[3 * kk] * h0 + T[3 * kk + 1] * h1 + T[3 * kk + 2] * h2;
+        }
+      } else {
+#pragma unroll
+        for (int b = 0; b < NEN; ++b) {
+          const double h0 = sG[q][b][0][le], h1 = sG[q][b][1][le], h2 = sG[q][b][2][le];
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk) acc[3 * b + kk] += T[3 * kk] * h0 + T[3 * kk + 1] * h1 + T[3 * kk + 2] * h2;
+        }
+      }
     }
+  };
+  if constexpr (SYMA) {
+    const int iu = __builtin_amdgcn_readfirstlane(i);
+    if (iu == 0)
+      points(Int<0>{});
+    else if (iu == 1)
+      points(Int<1>{});
+    else
+      points(Int<2>{});
+  } else {
+    points(Int<-1>{});
+  }
+  if constexpr (MODE == 2) {
+    // stage the block's tables in LDS (after every wave has left the point
+    // loop), then write them out contiguously: the E elements of a block are
+    // consecutive in the element-major tables
+    static_assert(E * ND == NT, "one staged residual value per thread");
+    double* stK = lds;           // [E][SP]
+    double* stR = lds + E * SP;  // [E][ND]
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d <= HN; ++d) {
+      if (d < HN || a < HN) {
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) stK[le * SP + sym_slot<NEN>(a, d) * 9 + 3 * i + kk] = acc[3 * d + kk];
+      }
+    }
+    stR[le * ND + rho] = rr;
+    __syncthreads();
+    const int64_t nvalid = e_end - eb < E ? e_end - eb : E;
+    if (tid < nvalid * ND) r_e[eb * ND + tid] = stR[tid];
+    double* dst = K_e + eb * NS;
+    for (int t = tid; t < nvalid * NS; t += NT) dst[t] = stK[(t / NS) * SP + t % NS];
+    return;
   }
   if (e >= e_end) return;
   if constexpr (MODE == 0) {
@@ -370,11 +477,6 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
 #pragma unroll
       for (int c = 0; c < ND; ++c) K_e[((int64_t)rho * ND + c) * n_el + e] = acc[c];
     }
-  } else if constexpr (MODE == 2) {
-    r_e[e * ND + rho] = rr;
-    double* dst = K_e + (e * ND + rho) * ND;
-#pragma unroll
-    for (int c = 0; c < ND; c += 2) *(double2*)(dst + c) = double2{acc[c], acc[c + 1]};
   } else {
     const int64_t R = 3 * (int64_t)conn[(int64_t)a * n_el + e] + i;
     if (r) r[R] += rr;
@@ -395,7 +497,8 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
 // ---------------------------------------------------------------- gather assembly
 // One wave per node i: rows 3i..3i+2 of the CSR values and of r are the sums,
 // over the node's (element e, local node a) pairs in incidence order
-// (ascending e), of rows 3a..3a+2 of K_e and r_e (element-major tables).  The
+// (ascending e), of rows 3a..3a+2 of K_e and r_e (element-major tables, K_e
+// in symmetric node blocks, see sym_slot).  The
 // three rows are accumulated in LDS and written once, contiguously (the rows
 // of one node share one column pattern and follow each other in CSR), so
 // every CSR value is written exactly once: no colouring, no atomics, no
@@ -409,6 +512,7 @@ __global__ void __launch_bounds__(256) k_gather_assemble(
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ e2csr, const double* __restrict__ Kw,
     const double* __restrict__ rw, double* __restrict__ r, double* __restrict__ vals, int max_row) {
   constexpr int ND = 3 * NEN, NB = 3 * ND, R = (NB + 63) / 64;
+  constexpr int NS = 9 * sym_blocks<NEN>(), HN = NEN / 2;
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t node = (int64_t)blockIdx.x * (blockDim.x / 64) + wv;
@@ -418,14 +522,15 @@ __global__ void __launch_bounds__(256) k_gather_assemble(
   const int len = (int)(row_ptr[3 * node + 1] - rb);
   if (len > max_row) return;  // caller's bound is wrong: leave the rows untouched rather than overrun LDS
   for (int t = lane; t < 3 * len; t += 64) acc[t] = 0.0;
-  // the entry t handled by this lane in round rr: row ii, node block b, column jj
-  int tb[R], tl[R];
+  // the entry t handled by this lane in round rr: row ii, node block b, column kk
+  int tb[R], tl[R], tik[R];
 #pragma unroll
   for (int rr = 0; rr < R; ++rr) {
     const int t = lane + 64 * rr;
     const int ii = t / ND, c = t % ND;
     tb[rr] = c / 3;
     tl[rr] = ii * len + c % 3;
+    tik[rr] = (ii << 2) | (c % 3);
   }
   double racc = 0.0;
   const int64_t k0 = inc_ptr[node], k1 = inc_ptr[node + 1];
@@ -438,14 +543,19 @@ __global__ void __launch_bounds__(256) k_gather_assemble(
       const int32_t ea = __builtin_amdgcn_readlane(mine, j);
       const int64_t e = ea / NEN;
       const int a = ea - (int)e * NEN;
-      const double* src = Kw + (e * ND + 3 * a) * ND;
+      const double* src = Kw + e * NS;
       const int32_t* off = e2csr + (int64_t)ea * NEN;
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
         const int t = lane + 64 * rr;
         if (t < NB) {
-          vv[rr] = src[t];
-          oo[rr] = off[tb[rr]];
+          // entry (ii, kk) of block (a, b): stored in a's slot, or transposed in b's
+          const int b = tb[rr], ii = tik[rr] >> 2, kk = tik[rr] & 3;
+          const int d = b >= a ? b - a : b - a + NEN;
+          const bool own = d < HN || (d == HN && a < HN);
+          const int k = own ? sym_slot<NEN>(a, d) * 9 + 3 * ii + kk : sym_slot<NEN>(b, NEN - d) * 9 + 3 * kk + ii;
+          vv[rr] = src[k];
+          oo[rr] = off[b];
         }
       }
       if (lane < 3) racc += rw[e * ND + 3 * a + lane];
