@@ -513,6 +513,7 @@ __global__ void __launch_bounds__(256) k_gather_assemble(
     const double* __restrict__ rw, double* __restrict__ r, double* __restrict__ vals, int max_row) {
   constexpr int ND = 3 * NEN, NB = 3 * ND, R = (NB + 63) / 64;
   constexpr int NS = 9 * sym_blocks<NEN>(), HN = NEN / 2;
+  constexpr int GB = 8;  // elements whose loads are in flight together
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t node = (int64_t)blockIdx.x * (blockDim.x / 64) + wv;
@@ -537,9 +538,7 @@ __global__ void __launch_bounds__(256) k_gather_assemble(
   for (int64_t kc = k0; kc < k1; kc += 64) {
     const int cnt = (int)((k1 - kc) < 64 ? (k1 - kc) : 64);
     const int32_t mine = lane < cnt ? inc_ent[kc + lane] : 0;
-    double v[R];
-    int o[R];
-    auto load = [&](int j, double (&vv)[R], int (&oo)[R]) {
+    auto load = [&](int j, double (&vv)[R], int (&oo)[R], double& rv) {
       const int32_t ea = __builtin_amdgcn_readlane(mine, j);
       const int64_t e = ea / NEN;
       const int a = ea - (int)e * NEN;
@@ -558,20 +557,28 @@ __global__ void __launch_bounds__(256) k_gather_assemble(
           oo[rr] = off[b];
         }
       }
-      if (lane < 3) racc += rw[e * ND + 3 * a + lane];
+      rv = lane < 3 ? rw[e * ND + 3 * a + lane] : 0.0;
     };
-    load(0, v, o);
-    for (int j = 0; j < cnt; ++j) {
-      double vn[R];
-      int on[R];
-      if (j + 1 < cnt) load(j + 1, vn, on);
+    // all loads of a batch of elements are in flight together; the batch is
+    // then added in incidence order with LDS adds that return nothing (one
+    // wave's LDS operations complete in issue order, and the lanes of one
+    // add target distinct entries, so the sums are formed in a fixed order)
+    for (int j0 = 0; j0 < cnt; j0 += GB) {
+      double v[GB][R], rv[GB];
+      int o[GB][R];
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) {
-        const int t = lane + 64 * rr;
-        if (t < NB && o[rr] >= 0) acc[tl[rr] + o[rr]] += v[rr];
+      for (int jj = 0; jj < GB; ++jj)
+        if (j0 + jj < cnt) load(j0 + jj, v[jj], o[jj], rv[jj]);
+#pragma unroll
+      for (int jj = 0; jj < GB; ++jj) {
+        if (j0 + jj >= cnt) break;
+        racc += rv[jj];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+          const int t = lane + 64 * rr;
+          if (t < NB && o[jj][rr] >= 0) atomicAdd(&acc[tl[rr] + o[jj][rr]], v[jj][rr]);
+        }
       }
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr) { v[rr] = vn[rr]; o[rr] = on[rr]; }
     }
   }
   if (vals)
