@@ -952,6 +952,12 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 
   __shared__ T W1s[P][H], B2s[P][H], c1s[H], c2s[H], as_[H];
   __shared__ double hb[HESS ? WPB : 1][HESS ? P2 : 1][16];
+  // FP64: the layer-2 and layer-1 matrix-core fragments are staged once per
+  // workgroup (LDS latency instead of L2 latency on every tile); FP32 reads
+  // them from the prepared tables, which leaves LDS for more resident waves
+  constexpr bool LT = PR == PREC_F64;
+  constexpr int NW1 = MB * S1 * 64, NA2 = MB * SH * 64, NG1 = HESS ? NPB * MB * 4 * 64 : 1;
+  __shared__ frag_t lW1[LT ? NW1 : 1], lA[LT ? NA2 : 1], lB[LT ? NW1 : 1], lATp[LT ? NA2 : 1], lG1[LT ? NG1 : 1];
 
   const bool dbl = std::is_same<T, double>::value;
   {
@@ -968,18 +974,36 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       c2s[i] = t_c[H + i];
       as_[i] = t_a[i];
     }
+    // layer 2 is index 1 of the per-layer fragment tables
+    const frag_t* gW1 = frag_ptr<E>(prep, lay, 0);
+    const frag_t* gA = frag_ptr<E>(prep, lay, 1) + NA2;
+    const frag_t* gB = frag_ptr<E>(prep, lay, 2) + NW1;
+    const frag_t* gATp = (const frag_t*)(prep + (dbl ? lay.x_ATp : lay.y_ATp)) + NA2;
+    const frag_t* gG1 = (const frag_t*)(prep + (dbl ? lay.x_G1 : lay.y_G1));
+    if constexpr (LT) {
+      for (int i = tid; i < NW1; i += 64 * WPB) {
+        lW1[i] = gW1[i];
+        lB[i] = gB[i];
+      }
+      for (int i = tid; i < NA2; i += 64 * WPB) {
+        lA[i] = gA[i];
+        lATp[i] = gATp[i];
+      }
+      if constexpr (HESS)
+        for (int i = tid; i < NG1; i += 64 * WPB) lG1[i] = gG1[i];
+    }
   }
+  const frag_t* fW1 = LT ? lW1 : frag_ptr<E>(prep, lay, 0);
+  const frag_t* fA = LT ? lA : frag_ptr<E>(prep, lay, 1) + NA2;
+  const frag_t* fB = LT ? lB : frag_ptr<E>(prep, lay, 2) + NW1;
+  const frag_t* fATp = LT ? lATp : (const frag_t*)(prep + (dbl ? lay.x_ATp : lay.y_ATp)) + NA2;
+  const frag_t* fG1 = LT ? lG1 : (const frag_t*)(prep + (dbl ? lay.x_G1 : lay.y_G1));
   __syncthreads();  // the only barrier: every wave reaches it before any exits
-  const int64_t tile = (int64_t)blockIdx.x * WPB + w;
-  if (tile * 16 >= n) return;
+  const double* d_b = (const double*)(prep + lay.d_b);
+  const int64_t ntiles = (n + 15) / 16;
+  auto tile_body = [&](int64_t tile) {
   const int64_t base = tile * 16, qp = base + q;
   const bool valid = qp < n;
-  const double* d_b = (const double*)(prep + lay.d_b);
-  const frag_t* fW1 = frag_ptr<E>(prep, lay, 0);
-  const frag_t* fA = frag_ptr<E>(prep, lay, 1);
-  const frag_t* fB = frag_ptr<E>(prep, lay, 2);
-  const frag_t* fATp = (const frag_t*)(prep + (dbl ? lay.x_ATp : lay.y_ATp));
-  const frag_t* fG1 = (const frag_t*)(prep + (dbl ? lay.x_G1 : lay.y_G1));
 
   frag_t kB[S1];
   double bK = 0.0;  // this lane's share of b . K, in FP64
@@ -1008,9 +1032,9 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   for (int ob = 0; ob < MB; ++ob) {
     frag_t AV[SH], BV[S1];
 #pragma unroll
-    for (int s = 0; s < SH; ++s) AV[s] = fA[((1 * MB + ob) * SH + s) * 64 + lane];
+    for (int s = 0; s < SH; ++s) AV[s] = fA[(ob * SH + s) * 64 + lane];
 #pragma unroll
-    for (int s = 0; s < S1; ++s) BV[s] = fB[((1 * MB + ob) * S1 + s) * 64 + lane];
+    for (int s = 0; s < S1; ++s) BV[s] = fB[(ob * S1 + s) * 64 + lane];
     const acc_t acc = mma_in<E, P>(BV, kB, mma_src<E, MB>(AV, z1, zero_acc<E>()));
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1034,7 +1058,7 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     for (int ob = 0; ob < MB; ++ob)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        acc = E::mma(fATp[((1 * MB + mb) * SH + 4 * ob + v) * 64 + lane], (frag_t)mu2[ob][v], acc);
+        acc = E::mma(fATp[(mb * SH + 4 * ob + v) * 64 + lane], (frag_t)mu2[ob][v], acc);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       mu1[mb][v] = (T)acc[v] * s1[mb][v];
@@ -1083,7 +1107,7 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     for (int ob = 0; ob < MB; ++ob) {
       frag_t AV[SH];
 #pragma unroll
-      for (int s = 0; s < SH; ++s) AV[s] = fA[((1 * MB + ob) * SH + s) * 64 + lane];
+      for (int s = 0; s < SH; ++s) AV[s] = fA[(ob * SH + s) * 64 + lane];
       T g2[4];  // gamma_2 of row block ob, selected without indexing registers at run time
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -1137,6 +1161,18 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       const int h = i / 16, qq = i % 16;
       if (base + qq < n) out[(int64_t)(1 + P + h) * n + base + qq] = hb[w][h][qq];
     }
+  }
+  };
+  if constexpr (LT) {
+    // persistent waves (the launcher sizes the grid to the resident
+    // workgroups): each takes every (gridDim.x * WPB)-th tile
+    for (int64_t tile = (int64_t)blockIdx.x * WPB + w; tile < ntiles; tile += (int64_t)gridDim.x * WPB) {
+      asm volatile("" ::: "memory");  // no fragment read is hoisted out of the tile loop
+      tile_body(tile);
+    }
+  } else {
+    const int64_t tile = (int64_t)blockIdx.x * WPB + w;
+    if (tile < ntiles) tile_body(tile);
   }
 }
 
@@ -1202,7 +1238,8 @@ static void launch_adj_one(const PrepLayout& lay, const unsigned char* prep, int
 template <int H, int P, int PR, bool HESS>
 static void launch_adj2_one(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
                             double* out, hipStream_t s) {
-  const unsigned grid = (unsigned)(((n + 15) / 16 + 3) / 4);
+  const int64_t nblk = ((n + 15) / 16 + 3) / 4;
+  const unsigned grid = PR == PREC_F64 ? persistent_grid(k_mlp_adj2<H, P, PR, HESS>, 256, nblk) : (unsigned)nblk;
   k_mlp_adj2<H, P, PR, HESS><<<grid, 256, 0, s>>>(prep, lay, n, K, out);
 }
 
