@@ -949,8 +949,10 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   constexpr int SH = H / 4, S1 = (P + 3) / 4, NPB = (P2 + 15) / 16;
   constexpr int WPB = 4;  // waves, one tile each, per workgroup
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
+  const uint32_t g8 = 8u * (uint32_t)g;
 
   __shared__ T W1s[P][H], B2s[P][H], c1s[H], c2s[H], as_[H];
+  __shared__ double db_s[P];
   __shared__ double hb[HESS ? WPB : 1][HESS ? P2 : 1][16];
   // FP64: the layer-2 and layer-1 matrix-core fragments are staged once per
   // workgroup (LDS latency instead of L2 latency on every tile); FP32 reads
@@ -974,6 +976,7 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       c2s[i] = t_c[H + i];
       as_[i] = t_a[i];
     }
+    for (int i = tid; i < P; i += 64 * WPB) db_s[i] = ((const double*)(prep + lay.d_b))[i];
     // layer 2 is index 1 of the per-layer fragment tables
     const frag_t* gW1 = frag_ptr<E>(prep, lay, 0);
     const frag_t* gA = frag_ptr<E>(prep, lay, 1) + NA2;
@@ -999,9 +1002,18 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   const frag_t* fATp = LT ? lATp : (const frag_t*)(prep + (dbl ? lay.x_ATp : lay.y_ATp)) + NA2;
   const frag_t* fG1 = LT ? lG1 : (const frag_t*)(prep + (dbl ? lay.x_G1 : lay.y_G1));
   __syncthreads();  // the only barrier: every wave reaches it before any exits
-  const double* d_b = (const double*)(prep + lay.d_b);
+  const double* d_b = db_s;
   const int64_t ntiles = (n + 15) / 16;
-  auto tile_body = [&](int64_t tile) {
+  // this lane's inputs of a tile: feature 4 s + g of point q
+  auto load_k = [&](int64_t tile, double (&kv)[S1]) {
+    const int64_t qq = tile * 16 + q;
+#pragma unroll
+    for (int s = 0; s < S1; ++s) {
+      const int m = 4 * s + g;
+      kv[s] = (qq < n && m < P) ? Kin[(int64_t)m * n + qq] : 0.0;
+    }
+  };
+  auto tile_body = [&](int64_t tile, const double (&kin)[S1]) {
   const int64_t base = tile * 16, qp = base + q;
   const bool valid = qp < n;
 
@@ -1010,9 +1022,8 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 #pragma unroll
   for (int s = 0; s < S1; ++s) {
     const int m = 4 * s + g;
-    const double kv = (valid && m < P) ? Kin[(int64_t)m * n + qp] : 0.0;
-    kB[s] = (T)kv;
-    if (m < P) bK += d_b[m] * kv;
+    kB[s] = (T)kin[s];
+    if (m < P) bK += d_b[m] * kin[s];
   }
   // ---- layer 1, every row block
   T z1[MB][4], s1[MB][4], t1[MB][4];
@@ -1138,8 +1149,13 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
           constexpr int h1 = (c0 + 1 < P2) ? packed_index(colmaj_n(c0 + 1), colmaj_m(c0 + 1), P) : 0;
           constexpr int h2 = (c0 + 2 < P2) ? packed_index(colmaj_n(c0 + 2), colmaj_m(c0 + 2), P) : 0;
           constexpr int h3 = (c0 + 3 < P2) ? packed_index(colmaj_n(c0 + 3), colmaj_m(c0 + 3), P) : 0;
-          const int h = g == 0 ? h0 : g == 1 ? h1 : g == 2 ? h2 : h3;
-          if (c0 + g < P2) hb[w][h][q] += r;
+          // lane group g's pair index, without a branch: four bytes of one constant
+          static_assert(P2 <= 256, "pair indices fit in a byte");
+          constexpr uint32_t hpack = (uint32_t)h0 | (uint32_t)h1 << 8 | (uint32_t)h2 << 16 | (uint32_t)h3 << 24;
+          const int h = (int)((hpack >> g8) & 0xffu);
+          // each lane adds to its own entry, and a wave's LDS operations
+          // complete in issue order: a fixed summation order without a wait
+          if (c0 + 3 < P2 || c0 + g < P2) __hip_atomic_fetch_add(&hb[w][h][q], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       };
       static_for<P>([&](auto MI) {
@@ -1165,14 +1181,28 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   };
   if constexpr (LT) {
     // persistent waves (the launcher sizes the grid to the resident
-    // workgroups): each takes every (gridDim.x * WPB)-th tile
-    for (int64_t tile = (int64_t)blockIdx.x * WPB + w; tile < ntiles; tile += (int64_t)gridDim.x * WPB) {
+    // workgroups): each takes every (gridDim.x * WPB)-th tile, with the
+    // next tile's inputs in flight while the current one is computed (the
+    // body issues no other global load, so nothing waits on them early)
+    const int64_t stride = (int64_t)gridDim.x * WPB;
+    double kn[S1];
+    int64_t tile = (int64_t)blockIdx.x * WPB + w;
+    if (tile < ntiles) load_k(tile, kn);
+    for (; tile < ntiles; tile += stride) {
       asm volatile("" ::: "memory");  // no fragment read is hoisted out of the tile loop
-      tile_body(tile);
+      double kc[S1];
+#pragma unroll
+      for (int s = 0; s < S1; ++s) kc[s] = kn[s];
+      if (tile + stride < ntiles) load_k(tile + stride, kn);
+      tile_body(tile, kc);
     }
   } else {
     const int64_t tile = (int64_t)blockIdx.x * WPB + w;
-    if (tile < ntiles) tile_body(tile);
+    if (tile < ntiles) {
+      double kc[S1];
+      load_k(tile, kc);
+      tile_body(tile, kc);
+    }
   }
 }
 
