@@ -73,12 +73,21 @@ def mlp_flops(kernel, h, L, p):
 
 
 def kernel_bytes_total(name, mesh, p):
-    """Algorithmic HBM bytes of one step for a bandwidth-bound kernel."""
+    """Algorithmic HBM bytes of one step for a bandwidth-bound kernel: every
+    input read once and every output written once.  The mesh recomputes
+    shape gradients and weights from the node coordinates inside gather_F and
+    the element integration, so those kernels read conn and X instead of
+    dN/dX and w."""
+    nen, nq, nd = mesh.nen, mesh.nq, 3 * mesh.nen
+    nodes = 8 * 3 * mesh.n_nodes                                  # one double triple per node (u or X)
     if name == "gather_assemble":
-        nd = 3 * mesh.nen
-        return mesh.n_el * (72 * sym_blocks(mesh.nen) + 8 * nd + 4 * mesh.nen * mesh.nen + 4 * mesh.nen) \
+        return mesh.n_el * (72 * sym_blocks(nen) + 8 * nd + 4 * nen * nen + 4 * nen) \
             + 8 * mesh.nnz + 8 * 3 * mesh.n_nodes + 8 * (3 * mesh.n_nodes + 1) + 8 * (mesh.n_nodes + 1)
-    b = kernel_bytes(name, mesh.nen, mesh.nq, p)
+    if name == "gather_F":
+        return mesh.n_el * (nq * 72 + 4 * nen) + 2 * nodes         # F out; conn, u and X in
+    if name == "integrate_elmajor":
+        return mesh.n_el * (nq * (72 + 216) + 4 * nen + 72 * sym_blocks(nen) + 8 * nd) + nodes
+    b = kernel_bytes(name, nen, nq, p)
     return None if b is None else b * mesh.n_el
 
 
@@ -88,27 +97,23 @@ def sym_blocks(nen):
 
 
 def kernel_bytes(name, nen, nq, p):
-    """Algorithmic HBM bytes per element for the bandwidth-bound kernels:
-    every input read once and every output written once (read-modify-write
-    counts twice)."""
+    """Algorithmic HBM bytes per element for the bandwidth-bound kernels that
+    read stored geometry (the coloured and table paths): every input read
+    once and every output written once (read-modify-write counts twice)."""
     nd = 3 * nen
     nout = 1 + p + p * (p + 1) // 2
-    per_qp = {"features": 72 + 8 * p, "chain": 72 + 8 * nout + 72 + 648, "gather_F": 8 * 3 * nen + 72}
+    per_qp = {"features": 72 + 8 * p, "chain": 72 + 8 * nout + 72 + 648}
     if name in per_qp:
         return nq * per_qp[name]
     if name == "material_cc":
         return nq * (72 + 8 * (nout - 1) + 8 * 27)              # F, network derivatives in; S~, CC~ out
-    inputs = nq * (72 + 8 * 27 + 8) + nq * nen * 3 * 8           # F, S~ and CC~, w, dN/dX
+    inputs = nq * (72 + 8 * 27) + 4 * nen                        # F, S~ and CC~, conn (geometry from X)
     if name == "integrate":
         return inputs + 8 * nd * nd + 8 * nd                     # K_e, r_e written
-    if name == "integrate_elmajor":
-        return inputs + 72 * sym_blocks(nen) + 8 * nd            # symmetric K_e, r_e written
     if name == "integrate_scatter":
         return inputs + 16 * nd * nd + 16 * nd + 4 * nen * nen   # CSR and r read-modify-write, CSR map
     if name == "assemble":
         return 24 * nd * nd + 24 * nd
-    if name == "fill":
-        return None
     return None
 
 

@@ -123,6 +123,14 @@ typedef struct {
   const int32_t* conn;   /* [nen][n_el] node ids                             */
   const double*  dNdX;   /* [nq][nen][3][n_el] reference shape gradients     */
   const double*  w;      /* [nq][n_el] Gauss weight * det(dX/dxi)            */
+  const double*  X;      /* [3][n_nodes] node coordinates, or NULL.  When
+                          * given, the tangent-build kernels recompute the
+                          * shape gradients and weights at each point from
+                          * X (the same arithmetic as pa_mesh_geometry, so
+                          * the same values) instead of reading dNdX and w,
+                          * which saves 8(3 nen + 1) bytes of traffic per
+                          * point and kernel; dNdX and w are still required
+                          * by the other entry points. */
 } pa_mesh;
 
 /* CSR matrix over node-major dofs (dof = 3*node + i). */

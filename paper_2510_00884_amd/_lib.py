@@ -30,7 +30,7 @@ class ModelDesc(C.Structure):
 
 class Mesh(C.Structure):
     _fields_ = [("n_el", C.c_int64), ("n_nodes", C.c_int64), ("nen", C.c_int32), ("nq", C.c_int32),
-                ("conn", C.c_void_p), ("dNdX", C.c_void_p), ("w", C.c_void_p)]
+                ("conn", C.c_void_p), ("dNdX", C.c_void_p), ("w", C.c_void_p), ("X", C.c_void_p)]
 
 
 class Csr(C.Structure):

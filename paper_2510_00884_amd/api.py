@@ -200,9 +200,12 @@ def voigt_unpack(tau, cc):
 class FEMesh:
     """Device-resident mesh: geometry, CSR pattern, element->CSR map and a
     colouring.  Elements are renumbered colour by colour (``perm[i]`` is the
-    original id of element i) so every colour is a contiguous range."""
+    original id of element i) so every colour is a contiguous range.
+    ``inline_geometry``: the tangent builds recompute shape gradients and
+    weights from the node coordinates instead of reading the stored ones
+    (same values, less memory traffic)."""
 
-    def __init__(self, X, conn, colour=None, device="cuda"):
+    def __init__(self, X, conn, colour=None, device="cuda", inline_geometry=True):
         self.lib = lib = L.load()
         X = np.ascontiguousarray(X, dtype=np.float64)
         conn = np.ascontiguousarray(conn, dtype=np.int32)
@@ -243,7 +246,7 @@ class FEMesh:
         self.col = torch.tensor(col, device=dev)
         self.e2csr = torch.empty((n_el, nen, nen), dtype=torch.int32, device=dev)
         self.c_mesh = L.Mesh(n_el, self.n_nodes, nen, self.nq, self.conn.data_ptr(), self.dNdX.data_ptr(),
-                             self.w.data_ptr())
+                             self.w.data_ptr(), self.X.data_ptr() if inline_geometry else None)
         self.c_csr = L.Csr(3 * self.n_nodes, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
                            self.e2csr.data_ptr())
         L.check(lib.pa_element_csr_map(C.byref(self.c_mesh), C.byref(self.c_csr), _p(self.e2csr), _stream()),

@@ -331,7 +331,7 @@ int element_front(const pa_model_desc* d, const void* prepared, int prec, const 
   const ModelConst mc = model_const(d);
   {
     Prof pr("gather_F", s);
-    launch_gather_F(m->nen, m->nq, m->n_el, m->conn, m->dNdX, u, F, s);
+    launch_gather_F(m->nen, m->nq, m->n_el, m->n_nodes, m->conn, m->dNdX, m->X, u, F, s);
   }
   {
     Prof pr("features", s);
@@ -365,7 +365,7 @@ int pa_element_residual_stiffness(const pa_model_desc* d, const void* prepared, 
   if ((rc = element_front(d, prepared, prec, m, u, n_bad, (unsigned char*)workspace, s, &F, &SC))) return rc;
   {
     Prof pr("integrate", s);
-    launch_chain_integrate(m->nen, m->n_el, 0, m->n_el, m->conn, m->dNdX, m->w, F, SC, r_e, K_e, nullptr,
+    launch_chain_integrate(m->nen, m->n_el, 0, m->n_el, m->conn, m->dNdX, m->w, m->n_nodes, m->X, F, SC, r_e, K_e, nullptr,
                            nullptr, nullptr, nullptr, 0, s);
   }
   return hip_check("pa_element_residual_stiffness");
@@ -403,7 +403,7 @@ int pa_tangent_build(const pa_model_desc* d, const void* prepared, int prec, con
   for (int k = 0; k < col->n_colours; ++k) {
     Prof pr("integrate_scatter", s);
     const int64_t b = col->colour_ptr[k], cnt = col->colour_ptr[k + 1] - b;
-    launch_chain_integrate(m->nen, m->n_el, b, cnt, m->conn, m->dNdX, m->w, F, SC, nullptr, nullptr, c->row_ptr,
+    launch_chain_integrate(m->nen, m->n_el, b, cnt, m->conn, m->dNdX, m->w, m->n_nodes, m->X, F, SC, nullptr, nullptr, c->row_ptr,
                            c->e2csr, r, vals, 1, s);
   }
   return hip_check("pa_tangent_build");
@@ -448,7 +448,7 @@ int pa_tangent_build_gather(const pa_model_desc* d, const void* prepared, int pr
   double* Kw = (double*)(tab + al(8 * nd * m->n_el));
   {
     Prof pr("integrate_elmajor", s);
-    launch_chain_integrate(m->nen, m->n_el, 0, m->n_el, m->conn, m->dNdX, m->w, F, SC, rw, Kw, nullptr, nullptr,
+    launch_chain_integrate(m->nen, m->n_el, 0, m->n_el, m->conn, m->dNdX, m->w, m->n_nodes, m->X, F, SC, rw, Kw, nullptr, nullptr,
                            nullptr, nullptr, 2, s);
   }
   {
@@ -509,7 +509,7 @@ int pa_residual_param_backward(const pa_model_desc* d, const void* prepared, int
   unsigned char* bws = ws + al(8 * 9 * n) + al(8 * 9 * n);
   {
     Prof pr("gather_F", s);
-    launch_gather_F(m->nen, m->nq, m->n_el, m->conn, m->dNdX, u, F, s);
+    launch_gather_F(m->nen, m->nq, m->n_el, m->n_nodes, m->conn, m->dNdX, m->X, u, F, s);
   }
   {
     Prof pr("residual_cotangent", s);

@@ -61,33 +61,28 @@ template <int NEN>
 __host__ __device__ inline constexpr int nq_of() { return NEN == 8 ? 8 : 4; }
 
 // ---------------------------------------------------------------- geometry
-template <int NEN>
-__global__ void __launch_bounds__(256) k_geometry(int64_t n_el, int64_t n_nodes, const double* __restrict__ X,
-                                                  const int32_t* __restrict__ conn, double* __restrict__ dNdX,
-                                                  double* __restrict__ w, int32_t* n_bad) {
-  constexpr int NQ = nq_of<NEN>();
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_el * NQ) return;
-  const int q = (int)(t / n_el);
-  const int64_t e = t % n_el;
-  double dN[NEN][3], wq;
+// Isoparametric map at reference point q of an element whose node
+// coordinates xn(a, J) returns (Sec. 2.1): the reference-coordinate
+// derivatives dN, the inverse Jacobian inv[J][d] = (dX/dxi)^{-1} and
+// det(dX/dxi); the shape gradients are dN^a/dX_J = sum_d inv[J][d] dN[a][d]
+// and the point weight w_q det.  Every kernel that needs the geometry calls
+// this, so stored and recomputed gradients agree bit for bit.
+template <int NEN, class XN>
+__device__ inline double geom_jac(int q, XN&& xn, double (&dN)[NEN][3], double (&inv)[3][3], double& wq) {
   ref_grads<NEN>(q, dN, wq);
   double jac[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // dX_J / dxi_d
 #pragma unroll
-  for (int a = 0; a < NEN; ++a) {
-    const int64_t node = conn[(int64_t)a * n_el + e];
+  for (int a = 0; a < NEN; ++a)
 #pragma unroll
     for (int J = 0; J < 3; ++J) {
-      const double x = X[J * n_nodes + node];
+      const double x = xn(a, J);
 #pragma unroll
       for (int d = 0; d < 3; ++d) jac[d][J] += dN[a][d] * x;
     }
-  }
   const double det = jac[0][0] * (jac[1][1] * jac[2][2] - jac[1][2] * jac[2][1])
                    - jac[0][1] * (jac[1][0] * jac[2][2] - jac[1][2] * jac[2][0])
                    + jac[0][2] * (jac[1][0] * jac[2][1] - jac[1][1] * jac[2][0]);
   const double r = 1.0 / det;
-  double inv[3][3];  // inverse of jac (as a matrix d x J): inv[J][d]
   inv[0][0] = (jac[1][1] * jac[2][2] - jac[1][2] * jac[2][1]) * r;
   inv[0][1] = (jac[0][2] * jac[2][1] - jac[0][1] * jac[2][2]) * r;
   inv[0][2] = (jac[0][1] * jac[1][2] - jac[0][2] * jac[1][1]) * r;
@@ -97,23 +92,42 @@ __global__ void __launch_bounds__(256) k_geometry(int64_t n_el, int64_t n_nodes,
   inv[2][0] = (jac[1][0] * jac[2][1] - jac[1][1] * jac[2][0]) * r;
   inv[2][1] = (jac[0][1] * jac[2][0] - jac[0][0] * jac[2][1]) * r;
   inv[2][2] = (jac[0][0] * jac[1][1] - jac[0][1] * jac[1][0]) * r;
+  return det;
+}
+
+__device__ inline double shape_grad(const double (&inv)[3][3], const double (&dNa)[3], int J) {
+  return inv[J][0] * dNa[0] + inv[J][1] * dNa[1] + inv[J][2] * dNa[2];
+}
+
+template <int NEN>
+__global__ void __launch_bounds__(256) k_geometry(int64_t n_el, int64_t n_nodes, const double* __restrict__ X,
+                                                  const int32_t* __restrict__ conn, double* __restrict__ dNdX,
+                                                  double* __restrict__ w, int32_t* n_bad) {
+  constexpr int NQ = nq_of<NEN>();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_el * NQ) return;
+  const int q = (int)(t / n_el);
+  const int64_t e = t % n_el;
+  double dN[NEN][3], inv[3][3], wq;
+  const double det = geom_jac<NEN>(
+      q, [&](int a, int J) { return X[J * n_nodes + conn[(int64_t)a * n_el + e]]; }, dN, inv, wq);
 #pragma unroll
   for (int a = 0; a < NEN; ++a)
 #pragma unroll
-    for (int J = 0; J < 3; ++J) {
-      const double v = inv[J][0] * dN[a][0] + inv[J][1] * dN[a][1] + inv[J][2] * dN[a][2];
-      dNdX[(((int64_t)q * NEN + a) * 3 + J) * n_el + e] = v;
-    }
+    for (int J = 0; J < 3; ++J) dNdX[(((int64_t)q * NEN + a) * 3 + J) * n_el + e] = shape_grad(inv, dN[a], J);
   w[(int64_t)q * n_el + e] = wq * det;
   if (n_bad && !(det > 0.0)) atomicAdd(n_bad, 1);
 }
 
 // ---------------------------------------------------------------- F at points
-// F_iJ = delta_iJ + sum_a u^a_i dN^a/dX_J; point index q*n_el + e.
-template <int NEN>
-__global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, const int32_t* __restrict__ conn,
-                                                  const double* __restrict__ dNdX, const double* __restrict__ u,
-                                                  double* __restrict__ F) {
+// F_iJ = delta_iJ + sum_a u^a_i dN^a/dX_J; point index q*n_el + e.  GI: the
+// shape gradients are recomputed from the node coordinates X [3][n_nodes]
+// (24 gathered, mostly cached values per point) instead of streaming the
+// stored 24 per point.
+template <int NEN, bool GI>
+__global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, int64_t n_nodes, const int32_t* __restrict__ conn,
+                                                  const double* __restrict__ dNdX, const double* __restrict__ X,
+                                                  const double* __restrict__ u, double* __restrict__ F) {
   constexpr int NQ = nq_of<NEN>();
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = n_el * NQ;
@@ -121,13 +135,17 @@ __global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, const int32_t* _
   const int q = (int)(t / n_el);
   const int64_t e = t % n_el;
   double f[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  int64_t node[NEN];
+#pragma unroll
+  for (int a = 0; a < NEN; ++a) node[a] = conn[(int64_t)a * n_el + e];
+  double dN[NEN][3], inv[3][3], wq;
+  if constexpr (GI) (void)geom_jac<NEN>(q, [&](int a, int J) { return X[J * n_nodes + node[a]]; }, dN, inv, wq);
 #pragma unroll
   for (int a = 0; a < NEN; ++a) {
-    const int64_t node = conn[(int64_t)a * n_el + e];
-    const double u0 = u[3 * node], u1 = u[3 * node + 1], u2 = u[3 * node + 2];
+    const double u0 = u[3 * node[a]], u1 = u[3 * node[a] + 1], u2 = u[3 * node[a] + 2];
 #pragma unroll
     for (int J = 0; J < 3; ++J) {
-      const double g = dNdX[(((int64_t)q * NEN + a) * 3 + J) * n_el + e];
+      const double g = GI ? shape_grad(inv, dN[a], J) : dNdX[(((int64_t)q * NEN + a) * 3 + J) * n_el + e];
       f[J] += u0 * g;
       f[3 + J] += u1 * g;
       f[6 + J] += u2 * g;
@@ -289,10 +307,11 @@ __host__ __device__ constexpr int sym_blocks() { return NEN * (NEN + 1) / 2; }
 // wave then runs a copy of the point loop specialised for its row, so every
 // LDS offset is an immediate.  Phase B: one thread per (row i, node a,
 // element) accumulates row 3a + i of K_e and r_e over the points.
-template <int NEN, int MODE>
-__global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
+template <int NEN, int MODE, bool GI>
+__global__ void __launch_bounds__(integrate_threads<NEN>()) __attribute__((amdgpu_waves_per_eu(3))) k_chain_integrate(
     int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* __restrict__ conn,
-    const double* __restrict__ dNdX, const double* __restrict__ w, const double* __restrict__ F,
+    const double* __restrict__ dNdX, const double* __restrict__ w, int64_t n_nodes, const double* __restrict__ X,
+    const double* __restrict__ F,
     const double* __restrict__ SC, double* __restrict__ r_e, double* __restrict__ K_e,
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ e2csr, double* __restrict__ r,
     double* __restrict__ vals) {
@@ -320,13 +339,16 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
   const int64_t e_end = e_begin + e_count;
   const int64_t n = n_el * NQ;
 
-  // this thread's shape-gradient value of every point slice: (b, J, le)
+  // this thread's shape-gradient value of every point slice: (b, J, le);
+  // with GI the phase-A threads recompute them from the node coordinates
   const int g_le = tid % E, g_J = (tid / E) % 3, g_b = tid / (3 * E);
   const int64_t g_e = eb + g_le;
   double gv[NQ];
+  if constexpr (!GI) {
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
-    gv[q] = (g_e < e_end) ? dNdX[(((int64_t)q * NEN + g_b) * 3 + g_J) * n_el + g_e] : 0.0;
+    for (int q = 0; q < NQ; ++q)
+      gv[q] = (g_e < e_end) ? dNdX[(((int64_t)q * NEN + g_b) * 3 + g_J) * n_el + g_e] : 0.0;
+  }
 
   // phase A: (point t = q * E + le, row i)
   if (tid < 3 * NPT) {
@@ -342,8 +364,23 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
       for (int c = 0; c < 6; ++c) S[c] = SC[(int64_t)c * n + pt];
 #pragma unroll
       for (int c = 0; c < 21; ++c) Cc[c] = SC[(int64_t)(6 + c) * n + pt];
-      wq = w[pt];
+      if constexpr (GI) {
+        // the isoparametric map of this point; row i writes column J = i of
+        // the shape gradients
+        double dN[NEN][3], inv[3][3], wr;
+        const double det = geom_jac<NEN>(
+            q, [&](int a, int J) { return X[J * n_nodes + conn[(int64_t)a * n_el + e]]; }, dN, inv, wr);
+        wq = wr * det;
+#pragma unroll
+        for (int a = 0; a < NEN; ++a) sG[q][a][i][le] = shape_grad(inv, dN[a], i);
+      } else {
+        wq = w[pt];
+      }
     } else {
+      if constexpr (GI) {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a) sG[q][a][i][le] = 0.0;
+      }
 #pragma unroll
       for (int c = 0; c < 9; ++c) Fm[c] = 0.0;
 #pragma unroll
@@ -380,8 +417,10 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) k_chain_integrate(
         }
     }
   }
+  if constexpr (!GI) {
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) sG[q][g_b][g_J][g_le] = gv[q];
+    for (int q = 0; q < NQ; ++q) sG[q][g_b][g_J][g_le] = gv[q];
+  }
   __syncthreads();
 
   // phase B: thread (row i, node a, element le), i outermost
@@ -659,36 +698,44 @@ int launch_geometry(int nen, int64_t n_el, int64_t n_nodes, const double* X, con
   return 0;
 }
 
-int launch_gather_F(int nen, int nq, int64_t n_el, const int32_t* conn, const double* dNdX,
-                    const double* u, double* F, hipStream_t s) {
+int launch_gather_F(int nen, int nq, int64_t n_el, int64_t n_nodes, const int32_t* conn, const double* dNdX,
+                    const double* X, const double* u, double* F, hipStream_t s) {
   if (n_el == 0) return 0;
-  PA_NEN_SWITCH(nen, (k_gather_F<8><<<nblocks(n_el * nq, 256), 256, 0, s>>>(n_el, conn, dNdX, u, F)),
-                (k_gather_F<10><<<nblocks(n_el * nq, 256), 256, 0, s>>>(n_el, conn, dNdX, u, F)));
+  const unsigned grid = nblocks(n_el * nq, 256);
+  if (X)
+    PA_NEN_SWITCH(nen, (k_gather_F<8, true><<<grid, 256, 0, s>>>(n_el, n_nodes, conn, dNdX, X, u, F)),
+                  (k_gather_F<10, true><<<grid, 256, 0, s>>>(n_el, n_nodes, conn, dNdX, X, u, F)));
+  else
+    PA_NEN_SWITCH(nen, (k_gather_F<8, false><<<grid, 256, 0, s>>>(n_el, n_nodes, conn, dNdX, X, u, F)),
+                  (k_gather_F<10, false><<<grid, 256, 0, s>>>(n_el, n_nodes, conn, dNdX, X, u, F)));
   return 0;
 }
-
 int launch_chain_integrate(int nen, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
-                           const double* dNdX, const double* w, const double* F, const double* SC,
-                           double* r_e, double* K_e, const int64_t* row_ptr, const int32_t* e2csr, double* r,
-                           double* vals, int mode, hipStream_t s) {
+                           const double* dNdX, const double* w, int64_t n_nodes, const double* X, const double* F,
+                           const double* SC, double* r_e, double* K_e, const int64_t* row_ptr, const int32_t* e2csr,
+                           double* r, double* vals, int mode, hipStream_t s) {
   if (e_count == 0) return 0;
-#define PA_INTEGRATE(NEN_)                                                                                          \
+#define PA_INTEGRATE_GI(NEN_, GI_)                                                                                 \
   {                                                                                                                \
     const unsigned grid = nblocks(e_count, 8);                                                                     \
     constexpr int nt = integrate_threads<NEN_>();                                                                  \
     if (mode == 1)                                                                                                 \
-      k_chain_integrate<NEN_, 1><<<grid, nt, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,       \
-                                                     row_ptr, e2csr, r, vals);                                     \
+      k_chain_integrate<NEN_, 1, GI_><<<grid, nt, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, n_nodes, X, F,    \
+                                                          SC, r_e, K_e, row_ptr, e2csr, r, vals);                 \
     else if (mode == 2)                                                                                            \
-      k_chain_integrate<NEN_, 2><<<grid, nt, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,       \
-                                                     row_ptr, e2csr, r, vals);                                     \
+      k_chain_integrate<NEN_, 2, GI_><<<grid, nt, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, n_nodes, X, F,    \
+                                                          SC, r_e, K_e, row_ptr, e2csr, r, vals);                 \
     else                                                                                                           \
-      k_chain_integrate<NEN_, 0><<<grid, nt, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, F, SC, r_e, K_e,       \
-                                                     row_ptr, e2csr, r, vals);                                     \
+      k_chain_integrate<NEN_, 0, GI_><<<grid, nt, 0, s>>>(n_el, e_begin, e_count, conn, dNdX, w, n_nodes, X, F,    \
+                                                          SC, r_e, K_e, row_ptr, e2csr, r, vals);                 \
   }
+#define PA_INTEGRATE(NEN_)            \
+  if (X) PA_INTEGRATE_GI(NEN_, true)  \
+  else PA_INTEGRATE_GI(NEN_, false)
   if (nen == 8) PA_INTEGRATE(8)
   else if (nen == 10) PA_INTEGRATE(10)
   else return -1;
+#undef PA_INTEGRATE_GI
 #undef PA_INTEGRATE
   return 0;
 }

@@ -92,12 +92,14 @@ int launch_param_backward(const PrepLayout& lay, const ThetaLayout& tl, int nsv,
 // elements and assembly (fe.hip)
 int launch_geometry(int nen, int64_t n_el, int64_t n_nodes, const double* X, const int32_t* conn,
                     double* dNdX, double* w, int32_t* n_bad, hipStream_t s);
-int launch_gather_F(int nen, int nq, int64_t n_el, const int32_t* conn, const double* dNdX,
-                    const double* u, double* F, hipStream_t s);
+// X [3][n_nodes] may be NULL; when given, the kernels recompute the shape
+// gradients and weights from it instead of reading dNdX and w
+int launch_gather_F(int nen, int nq, int64_t n_el, int64_t n_nodes, const int32_t* conn, const double* dNdX,
+                    const double* X, const double* u, double* F, hipStream_t s);
 int launch_chain_integrate(int nen, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
-                           const double* dNdX, const double* w, const double* F, const double* SC,
-                           double* r_e, double* K_e, const int64_t* row_ptr, const int32_t* e2csr, double* r,
-                           double* vals, int mode, hipStream_t s);
+                           const double* dNdX, const double* w, int64_t n_nodes, const double* X, const double* F,
+                           const double* SC, double* r_e, double* K_e, const int64_t* row_ptr, const int32_t* e2csr,
+                           double* r, double* vals, int mode, hipStream_t s);
 int launch_gather_assemble(int nen, int64_t n_nodes, const int64_t* inc_ptr, const int32_t* inc_ent,
                            const int64_t* row_ptr, const int32_t* e2csr, const double* Kw, const double* rw,
                            double* r, double* vals, int max_row, hipStream_t s);
