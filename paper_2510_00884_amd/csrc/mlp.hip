@@ -1131,14 +1131,17 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       // occupy 2 x 9 x 4 registers per lane)
       int zr = 0;
       asm volatile("" : "+v"(zr));
-      T J[P][4];
+      // gJ[n] = gamma_2 * (column n of J_2) for the columns formed so far; the
+      // column being paired, Jc, is held unscaled, so each pair term is one
+      // multiply-add: sum_r gamma_r J_rn J_rm = sum_r gJ_rn Jc_rm
+      T gJ[P][4], Jc[4];
       double pp[4];
       auto pair_sum = [&](auto TI) {
         constexpr int t = decltype(TI)::value;
-        constexpr int m = colmaj_m(t), nn = colmaj_n(t);
+        constexpr int nn = colmaj_n(t);
         T x = (T)0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) x += g2[v] * J[nn][v] * J[m][v];
+        for (int v = 0; v < 4; ++v) x += gJ[nn][v] * Jc[v];
         pp[t % 4] = (double)x;
         if constexpr (t % 4 == 3 || t == P2 - 1) {
           constexpr int c0 = t - t % 4;
@@ -1167,7 +1170,10 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
           for (int v = 0; v < 4; ++v) src[mb][v] = s1[mb][v] * W1s[m][16 * mb + E::row(g, v) + zr];
         const acc_t acc = mma_src<E, MB>(AV, src, zero_acc<E>());
 #pragma unroll
-        for (int v = 0; v < 4; ++v) J[m][v] = (T)acc[v] + B2s[m][16 * ob + E::row(g, v)];
+        for (int v = 0; v < 4; ++v) {
+          Jc[v] = (T)acc[v] + B2s[m][16 * ob + E::row(g, v)];
+          gJ[m][v] = g2[v] * Jc[v];
+        }
         static_for<m + 1>([&](auto NI) { pair_sum(std::integral_constant<int, m * (m + 1) / 2 + decltype(NI)::value>{}); });
       });
     }
