@@ -103,8 +103,12 @@ typedef enum { PA_MODEL_MICNN = 0, PA_MODEL_CANN = 1, PA_MODEL_GENT_THOMAS = 2 }
 typedef struct {
   int32_t n_sv;        /* number of structural vectors: 0, 1 or 2           */
   double  A[2][3];     /* reference structural vectors A^1, A^2              */
-  int32_t n_hidden;    /* L: hidden layers (2 or 3)                          */
-  int32_t width;       /* h: neurons per hidden layer (16, 32 or 64)         */
+  int32_t n_hidden;    /* L: hidden layers, 2, 3 or 4 (4: PA_ALGO_ADJOINT
+                        * and the parameter adjoint only; forward mode and
+                        * the BF16 precisions return PA_ERR_UNSUPPORTED)    */
+  int32_t width;       /* h: neurons per hidden layer: 1..16, 32 or 64.
+                        * Widths below 16 run zero-padded to 16 neurons
+                        * (same outputs, the cost of width 16)              */
   int32_t activation;  /* PA_ACT_SOFTPLUS                                    */
   int32_t normalize;   /* 1: energy- and stress-free reference state        */
   int32_t has_bias;    /* 1: hidden layers carry biases c_k                  */
@@ -163,7 +167,8 @@ typedef struct {
 /* ---------------------------------------------------------------- model */
 int32_t pa_num_inputs(const pa_model_desc* desc);
 int64_t pa_num_params(const pa_model_desc* desc);
-/* 1 if kernels exist for this (width, depth, inputs), else 0. */
+/* 1 if kernels exist for this (width, depth, inputs) with at least one
+ * algorithm, else 0 (depth 4: the adjoint form only). */
 int32_t pa_supported(const pa_model_desc* desc);
 /* Bytes of the prepared-parameter buffer. */
 size_t  pa_prepared_bytes(const pa_model_desc* desc);

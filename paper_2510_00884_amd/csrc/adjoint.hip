@@ -297,14 +297,15 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * w + E::row(g, v);
 #pragma unroll
-      for (int nb = 0; nb < MB; ++nb) out[tl.A[k] + (int64_t)r * H + 16 * nb + col] = (double)accA[k - 2][nb][v];
-      if (col < P) out[tl.B[k] + (int64_t)r * P + col] = (double)accB[k - 2][v];
+      for (int nb = 0; nb < MB; ++nb)
+        if (r < tl.H && 16 * nb + col < tl.H) out[tl.A[k] + (int64_t)r * tl.H + 16 * nb + col] = (double)accA[k - 2][nb][v];
+      if (col < P && r < tl.H) out[tl.B[k] + (int64_t)r * P + col] = (double)accB[k - 2][v];
     }
   });
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = 16 * w + E::row(g, v);
-    if (col < P) out[tl.W1 + (int64_t)r * P + col] = (double)accW1[v];
+    if (col < P && r < tl.H) out[tl.W1 + (int64_t)r * P + col] = (double)accW1[v];
   }
   // sums over the 16 points of each lane group
 #pragma unroll
@@ -313,13 +314,13 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const double sv = sum16((double)cacc[k - 1][v]);
-      if (off >= 0 && q == 0) out[off + 16 * w + E::row(g, v)] = sv;
+      if (off >= 0 && q == 0 && 16 * w + E::row(g, v) < tl.H) out[off + 16 * w + E::row(g, v)] = sv;
     }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const double sv = sum16((double)aacc[v]);
-    if (q == 0) out[tl.a + 16 * w + E::row(g, v)] = sv;
+    if (q == 0 && 16 * w + E::row(g, v) < tl.H) out[tl.a + 16 * w + E::row(g, v)] = sv;
   }
 #pragma unroll
   for (int s = 0; s < S1; ++s) {
@@ -353,7 +354,8 @@ int64_t param_backward_ws(int H, int L, int P, int prec, int64_t n) {
 #define PA_ADJ_CONFIGS(X) \
   X(16, 2, 3) X(16, 2, 5) X(16, 2, 9) X(16, 3, 3) X(16, 3, 5) X(16, 3, 9) \
   X(32, 2, 3) X(32, 2, 5) X(32, 2, 9) X(32, 3, 3) X(32, 3, 5) X(32, 3, 9) \
-  X(64, 2, 3) X(64, 2, 5) X(64, 2, 9) X(64, 3, 3) X(64, 3, 5) X(64, 3, 9)
+  X(64, 2, 3) X(64, 2, 5) X(64, 2, 9) X(64, 3, 3) X(64, 3, 5) X(64, 3, 9) \
+  X(16, 4, 3) X(16, 4, 5) X(16, 4, 9) X(32, 4, 3) X(32, 4, 5) X(32, 4, 9) X(64, 4, 3) X(64, 4, 5) X(64, 4, 9)
 
 int launch_param_backward(const PrepLayout& lay, const ThetaLayout& tl, int nsv, int prec,
                           const unsigned char* prep, const ModelConst& mc, int64_t n, const double* F,

@@ -96,7 +96,8 @@ int check_desc(const pa_model_desc* d) {
     return PA_OK;
   }
   if (d->n_hidden < 2) return fail(PA_ERR_ARG, "n_hidden must be >= 2 (got %d)", d->n_hidden);
-  if (d->width <= 0 || d->width % 16) return fail(PA_ERR_ARG, "width must be a positive multiple of 16 (got %d)", d->width);
+  if (d->width <= 0 || (d->width > 16 && d->width % 16))
+    return fail(PA_ERR_ARG, "width must be 1..16 or a multiple of 16 (got %d)", d->width);
   if (d->activation != PA_ACT_SOFTPLUS) return fail(PA_ERR_ARG, "unknown activation %d", d->activation);
   if (d->algorithm != PA_ALGO_FORWARD && d->algorithm != PA_ALGO_ADJOINT)
     return fail(PA_ERR_ARG, "unknown algorithm %d", d->algorithm);
@@ -104,7 +105,7 @@ int check_desc(const pa_model_desc* d) {
     for (int j = 0; j < 3; ++j)
       if (!std::isfinite(d->A[i][j])) return fail(PA_ERR_ARG, "structural vector %d is not finite", i);
   const int p = 3 + 2 * npair_of(d->n_sv);
-  if (!mlp_supported(d->width, d->n_hidden, p))
+  if (!mlp_supported(padded_width(d->width), d->n_hidden, p))
     return fail(PA_ERR_UNSUPPORTED, "no kernel for width %d, %d hidden layers, %d inputs", d->width, d->n_hidden, p);
   return PA_OK;
 }
@@ -122,7 +123,9 @@ ModelConst model_const(const pa_model_desc* d) {
 
 inline int p_of(const pa_model_desc* d) { return 3 + 2 * npair_of(d->n_sv); }
 
-inline PrepLayout layout_of(const pa_model_desc* d) { return prep_layout(d->width, d->n_hidden, p_of(d)); }
+inline PrepLayout layout_of(const pa_model_desc* d) {
+  return prep_layout(padded_width(d->width), d->n_hidden, p_of(d));
+}
 
 inline int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
 

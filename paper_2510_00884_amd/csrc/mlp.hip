@@ -94,15 +94,18 @@ ThetaLayout theta_layout(int H, int L, int P, int has_bias) {
 }
 
 // ---------------------------------------------------------------- prepare
+// Parameter accessors in the theta layout of width t.H; rows and columns at
+// or beyond t.H are the zero padding of a narrow network.
 __device__ inline double th_w(const double* th, const ThetaLayout& t, int k, int row, int col) {
+  if (row >= t.H || (k >= 2 && col >= t.H)) return 0.0;
   return (k == 1) ? th[t.W1 + (int64_t)row * t.P + col] : th[t.A[k] + (int64_t)row * t.H + col];
 }
 __device__ inline double th_skip(const double* th, const ThetaLayout& t, int k, int row, int m) {
-  return th[t.B[k] + (int64_t)row * t.P + m];
+  return row < t.H ? th[t.B[k] + (int64_t)row * t.P + m] : 0.0;
 }
 __device__ inline double th_c(const double* th, const ThetaLayout& t, int k, int row) {
   const int64_t o = (k == 1) ? t.c1 : t.c[k];
-  return o < 0 ? 0.0 : th[o + row];
+  return (o < 0 || row >= t.H) ? 0.0 : th[o + row];
 }
 
 __global__ void k_prep_tables(const double* __restrict__ th, ThetaLayout t, PrepLayout l,
@@ -120,7 +123,7 @@ __global__ void k_prep_tables(const double* __restrict__ th, ThetaLayout t, Prep
   const int64_t total = H + P + (int64_t)L * H + (int64_t)P * H + (int64_t)L * P * H + 8 + (int64_t)P * 16;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = i;
-    if (j < H) { double v = th[t.a + j]; d_a[j] = v; f_a[j] = (float)v; continue; }
+    if (j < H) { double v = j < t.H ? th[t.a + j] : 0.0; d_a[j] = v; f_a[j] = (float)v; continue; }
     j -= H;
     if (j < P) { d_b[j] = th[t.b + j]; continue; }
     j -= P;
@@ -1233,9 +1236,20 @@ static int launch_mlp_t(const PrepLayout& lay, int prec, const unsigned char* pr
   X(32, 2, 3) X(32, 2, 5) X(32, 2, 9) X(32, 3, 3) X(32, 3, 5) X(32, 3, 9) \
   X(64, 2, 3) X(64, 2, 5) X(64, 2, 9) X(64, 3, 3) X(64, 3, 5) X(64, 3, 9)
 
-bool mlp_supported(int H, int L, int P) {
+// adjoint-form kernels: the forward-mode configurations and four hidden layers
+#define PA_MLP_ADJ_CONFIGS(X) PA_MLP_CONFIGS(X) \
+  X(16, 4, 3) X(16, 4, 5) X(16, 4, 9) X(32, 4, 3) X(32, 4, 5) X(32, 4, 9) X(64, 4, 3) X(64, 4, 5) X(64, 4, 9)
+
+bool mlp_fwd_supported(int H, int L, int P) {
 #define PA_SUP(h, l, p) if (H == h && L == l && P == p) return true;
   PA_MLP_CONFIGS(PA_SUP)
+#undef PA_SUP
+  return false;
+}
+
+bool mlp_supported(int H, int L, int P) {
+#define PA_SUP(h, l, p) if (H == h && L == l && P == p) return true;
+  PA_MLP_ADJ_CONFIGS(PA_SUP)
 #undef PA_SUP
   return false;
 }
@@ -1315,7 +1329,7 @@ int launch_mlp(const PrepLayout& lay, int prec, int algo, const unsigned char* p
   if (algo == 1) {
 #define PA_DISPATCH_ADJ(h, l, p) \
     if (lay.H == h && lay.L == l && lay.P == p) return launch_mlp_adj_t<h, l, p>(lay, prec, prep, n, K, out, hess, s);
-    PA_MLP_CONFIGS(PA_DISPATCH_ADJ)
+    PA_MLP_ADJ_CONFIGS(PA_DISPATCH_ADJ)
 #undef PA_DISPATCH_ADJ
     return -2;
   }
@@ -1332,7 +1346,8 @@ int launch_prepare(const PrepLayout& lay, const ThetaLayout& tl, const double* t
   k_prep_tables<<<64, 256, 0, s>>>(theta, tl, lay, prep);
   k_prep_frags<<<256, 256, 0, s>>>(theta, tl, lay, prep);
   if (normalize) {
-    int rc = launch_mlp(lay, PREC_F64, 0, prep, 1, (const double*)(prep + lay.k0),
+    const int algo = mlp_fwd_supported(lay.H, lay.L, lay.P) ? 0 : 1;
+    int rc = launch_mlp(lay, PREC_F64, algo, prep, 1, (const double*)(prep + lay.k0),
                         (double*)(prep + lay.nout), 1, s);
     if (rc) return rc;
   }

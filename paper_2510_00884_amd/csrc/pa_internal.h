@@ -39,11 +39,18 @@ struct PrepLayout {
 struct ThetaLayout {
   int32_t H, L, P, has_bias;
   int64_t W1, c1;     // c1 < 0 when absent
-  int64_t A[4], B[4], c[4];  // per layer k (index k), k >= 2
+  int64_t A[5], B[5], c[5];  // per layer k (index k), 2 <= k <= 4
   int64_t a, b, total;
 };
 
 PrepLayout prep_layout(int H, int L, int P);
+// Widths below 16 run on one 16-row matrix-core tile: the prepared tables
+// hold the network zero-padded to 16 neurons (padded neurons have zero
+// incoming, outgoing and output weights, so they change no output).
+inline int padded_width(int h) { return h < 16 ? 16 : h; }
+// Forward-mode (Alg. 4) kernels exist for 2-3 hidden layers; the
+// adjoint-form kernels also for 4.
+bool mlp_fwd_supported(int H, int L, int P);
 
 // Inner functions other than the MICNN (closed.hip); values match pa_model_kind.
 enum { MODEL_MICNN = 0, MODEL_CANN = 1, MODEL_GENT_THOMAS = 2 };

@@ -45,7 +45,8 @@ def _desc(n_sv=2, h=32, Ld=2, has_bias=1):
     return d
 
 
-@pytest.mark.parametrize("n_sv,h,Ld,bias", [(0, 16, 2, 1), (1, 16, 2, 1), (2, 32, 2, 1), (2, 64, 3, 1), (0, 16, 3, 0)])
+@pytest.mark.parametrize("n_sv,h,Ld,bias", [(0, 16, 2, 1), (1, 16, 2, 1), (2, 32, 2, 1), (2, 64, 3, 1), (0, 16, 3, 0),
+                                            (2, 8, 2, 1), (1, 2, 3, 0), (2, 64, 4, 1), (0, 4, 4, 1)])
 def test_sizes_match_generators(lib, n_sv, h, Ld, bias):
     d = _desc(n_sv, h, Ld, bias)
     p = synth.num_inputs(n_sv)
@@ -63,6 +64,10 @@ def test_argument_errors_before_launch(lib):
     assert b"n_sv" in lib.pa_last_error()
     d = _desc(h=48)
     assert lib.pa_prepare_params(C.byref(d), C.c_void_p(8), C.c_void_p(8), None) == L.PA_ERR_UNSUPPORTED
+    d = _desc(h=20)  # above 16 a width must be a multiple of 16
+    assert lib.pa_prepare_params(C.byref(d), C.c_void_p(8), C.c_void_p(8), None) == L.PA_ERR_ARG
+    d = _desc(Ld=5)
+    assert lib.pa_supported(C.byref(d)) == 0
     d = _desc()
     rc = lib.pa_energy_stress_tangent(C.byref(d), C.c_void_p(8), 0, -1, None, None, None, None, None, None, 0, None)
     assert rc == L.PA_ERR_ARG

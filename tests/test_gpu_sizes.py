@@ -1,0 +1,124 @@
+"""GPU parity across network sizes outside the mesh configurations: widths
+below 16 (zero-padded to one 16-row matrix-core tile) and four hidden
+layers (adjoint form only), against the FP64 oracle on seeded inputs with
+full 16-point tiles and a ragged tail.  Tolerances (normwise): FP64 1e-12
+for Psi, P and the tangent, 1e-10 for the parameter adjoint; FP32 network
+1e-5 (tangent) and 1e-4 (parameter adjoint)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import calib, fe, ncm
+from paper_2510_00884_amd import synth
+from paper_2510_00884_amd._lib import PaError
+from gpu_util import close, need_gpu, rel, say
+
+pytestmark = pytest.mark.gpu
+
+# (n_sv, width, hidden layers)
+SIZES = [(2, 8, 2), (1, 4, 3), (0, 2, 2), (2, 16, 4), (1, 32, 4), (2, 64, 4)]
+
+
+def build(api, n_sv, h, L, normalize=True, algorithm="adjoint", has_bias=True):
+    p = synth.num_inputs(n_sv)
+    theta = synth.micnn_params(p, h, L, seed=1, has_bias=has_bias)
+    Av = synth.structural_vectors(n_sv)
+    gm = api.Model(theta, n_sv, h, L, A=Av, normalize=normalize, algorithm=algorithm, has_bias=has_bias)
+    om = ncm.model_from_theta(theta, p, h, L, Av, normalize=normalize, has_bias=has_bias)
+    return gm, om, theta, p, Av
+
+
+def unpack(out, n):
+    return (out["psi"].cpu().numpy(), out["P"].cpu().numpy().T.reshape(n, 3, 3),
+            out["A"].cpu().numpy().T.reshape(n, 3, 3, 3, 3))
+
+
+@pytest.mark.parametrize("n_sv,h,L", SIZES)
+def test_adjoint_fp64_sizes(n_sv, h, L):
+    api = need_gpu()
+    say("sizes adjoint fp64", n_sv, h, L)
+    gm, om, *_ = build(api, n_sv, h, L)
+    n = 1000
+    F = synth.sample_F(n, seed=0)
+    psi, P, A = unpack(api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec="fp64"), n)
+    ref = ncm.stress_stiffness(F, om)
+    close(psi, ref["psi"], 1e-12, "psi")
+    close(P, ref["P"], 1e-12, "P")
+    close(A, ref["A"], 1e-12, "A")
+
+
+@pytest.mark.parametrize("n_sv,h,L", [(2, 8, 2), (2, 32, 4)])
+def test_adjoint_fp32_sizes(n_sv, h, L):
+    api = need_gpu()
+    say("sizes adjoint fp32", n_sv, h, L)
+    gm, om, *_ = build(api, n_sv, h, L)
+    n = 1000
+    F = synth.sample_F(n, seed=5)
+    psi, P, A = unpack(api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec="fp32"), n)
+    ref = ncm.stress_stiffness(F, om)
+    e = (rel(psi, ref["psi"]), rel(P, ref["P"]), rel(A, ref["A"]))
+    say("  errors psi/P/A", e)
+    assert max(e) < 1e-5
+
+
+@pytest.mark.parametrize("n_sv,h,L", [(2, 8, 2), (1, 4, 3)])
+def test_forward_mode_narrow(n_sv, h, L):
+    """The forward-mode kernel (Alg. 4) on a zero-padded narrow network."""
+    api = need_gpu()
+    say("sizes forward fp64", n_sv, h, L)
+    gm, om, *_ = build(api, n_sv, h, L, algorithm="forward")
+    n = 1000
+    F = synth.sample_F(n, seed=0)
+    psi, P, A = unpack(api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec="fp64"), n)
+    ref = ncm.stress_stiffness(F, om)
+    close(psi, ref["psi"], 1e-12, "psi")
+    close(A, ref["A"], 1e-12, "A")
+
+
+def test_depth4_forward_mode_and_bf16_unsupported():
+    api = need_gpu()
+    say("sizes depth 4 unsupported paths")
+    F = torch.tensor(synth.sample_F(32, seed=5), device="cuda")
+    gm, *_ = build(api, 2, 16, 4, algorithm="forward")
+    with pytest.raises(PaError):
+        api.energy_stress_tangent(gm, F, prec="fp64")
+    gm, *_ = build(api, 2, 16, 4, algorithm="adjoint")
+    with pytest.raises(PaError):
+        api.energy_stress_tangent(gm, F, prec="bf16")
+
+
+@pytest.mark.parametrize("n_sv,h,L,bias", [(2, 8, 2, True), (1, 4, 3, False), (2, 16, 4, True), (1, 32, 4, True)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_param_backward_sizes(n_sv, h, L, bias, prec, tol):
+    api = need_gpu()
+    say("sizes param_backward", n_sv, h, L, bias, prec)
+    gm, om, theta, p, Av = build(api, n_sv, h, L, normalize=False, has_bias=bias)
+    n = 700
+    F = synth.sample_F(n, seed=3)
+    Pbar = synth.rng(7).normal(size=(n, 3, 3))
+    K, g = calib.feature_grads(F, Av)
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    Pt = calib.stress_from_theta(th, torch.tensor(K), torch.tensor(g), p, h, L, bias)
+    ref, = torch.autograd.grad(Pt, th, torch.tensor(Pbar))
+    tb = api.param_backward(gm, torch.tensor(F, device="cuda"), torch.tensor(Pbar, device="cuda"), prec=prec)
+    assert tb.numel() == synth.num_params(p, h, L, bias)
+    e = close(tb.cpu().numpy(), ref.numpy(), tol, "theta_bar")
+    say("  err", e)
+
+
+def test_tangent_build_depth4():
+    """A hex8 tangent build with a four-layer network (adjoint form)."""
+    api = need_gpu()
+    say("sizes tangent build depth 4")
+    n = 3
+    X, conn, par = synth.hex_mesh(n)
+    u = synth.displacement_modes(X, 1.0 / n, seed=0)
+    gm, om, *_ = build(api, 2, 16, 4)
+    mesh = api.FEMesh(X, conn, colour=par)
+    cperm = conn[mesh.perm]
+    dNdX, w, _ = fe.geometry(X, cperm)
+    r_ref, K_ref, _ = fe.element_residual_stiffness(u, cperm, dNdX, w, om)
+    rg, Kg = fe.assemble(cperm, r_ref, K_ref, X.shape[0])
+    r, vals = api.tangent_build(gm, mesh, torch.tensor(u, device="cuda"), prec="fp64")
+    close(r.cpu().numpy(), rg, 1e-12, "r")
+    close(vals.cpu().numpy(), Kg.data, 1e-12, "vals")
