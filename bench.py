@@ -242,7 +242,8 @@ def other_workload(args):
         n = 1 << 20
         F = torch.tensor(synth.sample_F(n, seed=0), device="cuda")
         res = {}
-        cases = [("micnn", w_, l_) for l_ in (2, 3) for w_ in (16, 32, 64)] + [("cann", 0, 0), ("gent_thomas", 0, 0)]
+        # widths below 16 run zero-padded to 16 neurons
+        cases = [("micnn", w_, l_) for l_ in (2, 3, 4) for w_ in (2, 8, 16, 32, 64)] + [("cann", 0, 0), ("gent_thomas", 0, 0)]
         for kind, w_, l_ in cases:
             if kind == "micnn":
                 th = synth.micnn_params(p, w_, l_, seed=1)
