@@ -84,7 +84,7 @@ def kernel_bytes_total(name, mesh, p):
         return mesh.n_el * (72 * sym_blocks(nen) + 8 * nd + 4 * nen * nen + 4 * nen) \
             + 8 * mesh.nnz + 8 * 3 * mesh.n_nodes + 8 * (3 * mesh.n_nodes + 1) + 8 * (mesh.n_nodes + 1)
     if name == "gather_F":
-        return mesh.n_el * (nq * 72 + 4 * nen) + 2 * nodes         # F out; conn, u and X in
+        return mesh.n_el * (nq * (72 + 8 * p) + 4 * nen) + 2 * nodes  # F and K out; conn, u and X in
     if name == "integrate_elmajor":
         return mesh.n_el * (nq * (72 + 216) + 4 * nen + 72 * sym_blocks(nen) + 8 * nd) + nodes
     b = kernel_bytes(name, nen, nq, p)

@@ -333,12 +333,8 @@ int element_front(const pa_model_desc* d, const void* prepared, int prec, const 
   double* Nout = (double*)(mws + al(8 * (int64_t)p * n));
   const ModelConst mc = model_const(d);
   {
-    Prof pr("gather_F", s);
-    launch_gather_F(m->nen, m->nq, m->n_el, m->n_nodes, m->conn, m->dNdX, m->X, u, F, s);
-  }
-  {
-    Prof pr("features", s);
-    launch_features(d->n_sv, n, F, mc, K, n_bad, s);
+    Prof pr("gather_F", s);  // F and the network inputs in one pass
+    launch_gather_F(m->nen, m->nq, m->n_el, m->n_nodes, m->conn, m->dNdX, m->X, u, F, d->n_sv, &mc, K, n_bad, s);
   }
   int rc = run_inner(d, prepared, prec, n, K, Nout, 1, s);
   if (rc) return rc;
@@ -512,7 +508,7 @@ int pa_residual_param_backward(const pa_model_desc* d, const void* prepared, int
   unsigned char* bws = ws + al(8 * 9 * n) + al(8 * 9 * n);
   {
     Prof pr("gather_F", s);
-    launch_gather_F(m->nen, m->nq, m->n_el, m->n_nodes, m->conn, m->dNdX, m->X, u, F, s);
+    launch_gather_F(m->nen, m->nq, m->n_el, m->n_nodes, m->conn, m->dNdX, m->X, u, F, -1, nullptr, nullptr, nullptr, s);
   }
   {
     Prof pr("residual_cotangent", s);

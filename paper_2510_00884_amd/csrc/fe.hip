@@ -123,11 +123,14 @@ __global__ void __launch_bounds__(256) k_geometry(int64_t n_el, int64_t n_nodes,
 // F_iJ = delta_iJ + sum_a u^a_i dN^a/dX_J; point index q*n_el + e.  GI: the
 // shape gradients are recomputed from the node coordinates X [3][n_nodes]
 // (24 gathered, mostly cached values per point) instead of streaming the
-// stored 24 per point.
-template <int NEN, bool GI>
+// stored 24 per point.  NSV >= 0: the network inputs K [p][n] (features of
+// App. C with NSV structural vectors) are formed from F in registers too,
+// and points with J <= 0 or non-finite F are counted in n_bad.
+template <int NEN, bool GI, int NSV>
 __global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, int64_t n_nodes, const int32_t* __restrict__ conn,
                                                   const double* __restrict__ dNdX, const double* __restrict__ X,
-                                                  const double* __restrict__ u, double* __restrict__ F) {
+                                                  const double* __restrict__ u, double* __restrict__ F,
+                                                  ModelConst mc, double* __restrict__ K, int32_t* n_bad) {
   constexpr int NQ = nq_of<NEN>();
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = n_el * NQ;
@@ -153,6 +156,15 @@ __global__ void __launch_bounds__(256) k_gather_F(int64_t n_el, int64_t n_nodes,
   }
 #pragma unroll
   for (int c = 0; c < 9; ++c) F[(int64_t)c * n + t] = f[c];
+  if constexpr (NSV >= 0) {
+    Kin k;
+    kin_compute<NSV>(f, mc, k);
+    count_bad(n_bad, !(k.J > 0.0 && finite9(f)));
+    double kf[Feat<NSV>::P];
+    kin_features<NSV>(k, mc, kf);
+#pragma unroll
+    for (int m = 0; m < Feat<NSV>::P; ++m) K[m * n + t] = kf[m];
+  }
 }
 
 // ---------------------------------------------------------------- residual-loss cotangent
@@ -699,15 +711,31 @@ int launch_geometry(int nen, int64_t n_el, int64_t n_nodes, const double* X, con
 }
 
 int launch_gather_F(int nen, int nq, int64_t n_el, int64_t n_nodes, const int32_t* conn, const double* dNdX,
-                    const double* X, const double* u, double* F, hipStream_t s) {
+                    const double* X, const double* u, double* F, int nsv, const ModelConst* mc, double* K,
+                    int32_t* n_bad, hipStream_t s) {
   if (n_el == 0) return 0;
   const unsigned grid = nblocks(n_el * nq, 256);
-  if (X)
-    PA_NEN_SWITCH(nen, (k_gather_F<8, true><<<grid, 256, 0, s>>>(n_el, n_nodes, conn, dNdX, X, u, F)),
-                  (k_gather_F<10, true><<<grid, 256, 0, s>>>(n_el, n_nodes, conn, dNdX, X, u, F)));
-  else
-    PA_NEN_SWITCH(nen, (k_gather_F<8, false><<<grid, 256, 0, s>>>(n_el, n_nodes, conn, dNdX, X, u, F)),
-                  (k_gather_F<10, false><<<grid, 256, 0, s>>>(n_el, n_nodes, conn, dNdX, X, u, F)));
+  const ModelConst m0 = mc ? *mc : ModelConst{};
+  if (!K) nsv = -1;
+#define PA_GF(NEN_, GI_, NSV_) \
+  k_gather_F<NEN_, GI_, NSV_><<<grid, 256, 0, s>>>(n_el, n_nodes, conn, dNdX, X, u, F, m0, K, n_bad)
+#define PA_GF_NSV(NEN_, GI_)          \
+  switch (nsv) {                      \
+    case -1: PA_GF(NEN_, GI_, -1); break; \
+    case 0: PA_GF(NEN_, GI_, 0); break;   \
+    case 1: PA_GF(NEN_, GI_, 1); break;   \
+    case 2: PA_GF(NEN_, GI_, 2); break;   \
+    default: return -1;               \
+  }
+  if (nen == 8) {
+    if (X) PA_GF_NSV(8, true) else PA_GF_NSV(8, false)
+  } else if (nen == 10) {
+    if (X) PA_GF_NSV(10, true) else PA_GF_NSV(10, false)
+  } else {
+    return -1;
+  }
+#undef PA_GF_NSV
+#undef PA_GF
   return 0;
 }
 int launch_chain_integrate(int nen, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,

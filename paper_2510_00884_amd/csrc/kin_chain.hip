@@ -7,19 +7,6 @@
 
 namespace pa {
 
-// Wave-aggregated increment of an optional device counter.
-__device__ inline void count_bad(int32_t* n_bad, bool bad) {
-  if (!n_bad) return;
-  const unsigned long long m = __ballot(bad);
-  if (m && (threadIdx.x & 63) == (__ffsll((long long)m) - 1)) atomicAdd(n_bad, (int32_t)__popcll(m));
-}
-
-__device__ inline bool finite9(const double* F) {
-  bool ok = true;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) ok = ok && isfinite(F[i]);
-  return ok;
-}
 
 template <int NSV>
 __global__ void __launch_bounds__(256) k_invariants(int64_t n, const double* __restrict__ F,

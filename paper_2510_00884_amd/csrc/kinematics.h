@@ -23,6 +23,20 @@
 
 namespace pa {
 
+// Wave-aggregated increment of an optional device counter.
+__device__ inline void count_bad(int32_t* n_bad, bool bad) {
+  if (!n_bad) return;
+  const unsigned long long m = __ballot(bad);
+  if (m && (threadIdx.x & 63) == (__ffsll((long long)m) - 1)) atomicAdd(n_bad, (int32_t)__popcll(m));
+}
+
+__device__ inline bool finite9(const double* F) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) ok = ok && isfinite(F[i]);
+  return ok;
+}
+
 struct ModelConst {
   double A[2][3];      // structural vectors A^1, A^2
   double AdotA[3];     // A^i . A^j for the pairs below

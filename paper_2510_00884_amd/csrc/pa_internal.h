@@ -101,8 +101,11 @@ int launch_geometry(int nen, int64_t n_el, int64_t n_nodes, const double* X, con
                     double* dNdX, double* w, int32_t* n_bad, hipStream_t s);
 // X [3][n_nodes] may be NULL; when given, the kernels recompute the shape
 // gradients and weights from it instead of reading dNdX and w
+// nsv >= 0 with K non-NULL: also the network inputs K [p][n] and the
+// inverted-point count (the features kernel's outputs)
 int launch_gather_F(int nen, int nq, int64_t n_el, int64_t n_nodes, const int32_t* conn, const double* dNdX,
-                    const double* X, const double* u, double* F, hipStream_t s);
+                    const double* X, const double* u, double* F, int nsv, const ModelConst* mc, double* K,
+                    int32_t* n_bad, hipStream_t s);
 int launch_chain_integrate(int nen, int64_t n_el, int64_t e_begin, int64_t e_count, const int32_t* conn,
                            const double* dNdX, const double* w, int64_t n_nodes, const double* X, const double* F,
                            const double* SC, double* r_e, double* K_e, const int64_t* row_ptr, const int32_t* e2csr,
