@@ -400,31 +400,39 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) __attribute__((amdgp
 #pragma unroll
       for (int c = 0; c < 21; ++c) Cc[c] = 0.0;
     }
-    double Fi[3];  // row i of F
+    // row i of F scaled by 4 w (tangent) and 2 w (stress and the S~ term)
+    const double w2 = 2.0 * wq, w4 = 4.0 * wq;
+    double Fi[3], Fi4[3];
 #pragma unroll
-    for (int I = 0; I < 3; ++I) Fi[I] = (i == 0) ? Fm[I] : (i == 1) ? Fm[3 + I] : Fm[6 + I];
+    for (int I = 0; I < 3; ++I) {
+      Fi[I] = (i == 0) ? Fm[I] : (i == 1) ? Fm[3 + I] : Fm[6 + I];
+      Fi4[I] = w4 * Fi[I];
+    }
 #pragma unroll
     for (int J = 0; J < 3; ++J) {
-      sP[(3 * i + J) * NPT + t] = wq * 2.0 * (Fi[0] * S[VI(0, J)] + Fi[1] * S[VI(1, J)] + Fi[2] * S[VI(2, J)]);
-      // Y_KL = sum_I F_iI CC~_IJKL
+      sP[(3 * i + J) * NPT + t] = w2 * (Fi[0] * S[VI(0, J)] + Fi[1] * S[VI(1, J)] + Fi[2] * S[VI(2, J)]);
+      // Y_KL = 4 w sum_I F_iI CC~_IJKL
       double Y[3][3];
 #pragma unroll
       for (int K = 0; K < 3; ++K)
 #pragma unroll
         for (int L = 0; L < 3; ++L)
-          Y[K][L] = Fi[0] * Cc[TRI(VI(0, J), VI(K, L))] + Fi[1] * Cc[TRI(VI(1, J), VI(K, L))] +
-                    Fi[2] * Cc[TRI(VI(2, J), VI(K, L))];
+          Y[K][L] = Fi4[0] * Cc[TRI(VI(0, J), VI(K, L))] + Fi4[1] * Cc[TRI(VI(1, J), VI(K, L))] +
+                    Fi4[2] * Cc[TRI(VI(2, J), VI(K, L))];
 #pragma unroll
       for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int L = 0; L < 3; ++L) {
-          double v = 4.0 * (Fm[3 * k] * Y[0][L] + Fm[3 * k + 1] * Y[1][L] + Fm[3 * k + 2] * Y[2][L]);
-          if (k == i) v += 2.0 * S[VI(J, L)];
+          // w AA_iJkL = 2 w delta_ik S~_JL + F_kK Y_KL
+          double v = (k == i) ? w2 * S[VI(J, L)] : 0.0;
+          v = fma(Fm[3 * k], Y[0][L], v);
+          v = fma(Fm[3 * k + 1], Y[1][L], v);
+          v = fma(Fm[3 * k + 2], Y[2][L], v);
           const int al = 3 * i + J, be = 3 * k + L;
           if constexpr (SYMA) {
-            if (al <= be) sA[SYM9(al, be) * NPT + t] = wq * v;
+            if (al <= be) sA[SYM9(al, be) * NPT + t] = v;
           } else {
-            sA[(al * 9 + be) * NPT + t] = wq * v;
+            sA[(al * 9 + be) * NPT + t] = v;
           }
         }
     }
@@ -469,21 +477,25 @@ __global__ void __launch_bounds__(integrate_threads<NEN>()) __attribute__((amdgp
         }
         T[c] = x;
       }
+      // three multiply-adds straight into the accumulator per entry
+      auto add_block = [&](int c, double h0, double h1, double h2) {
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          double x = acc[c + kk];
+          x = fma(T[3 * kk], h0, x);
+          x = fma(T[3 * kk + 1], h1, x);
+          acc[c + kk] = fma(T[3 * kk + 2], h2, x);
+        }
+      };
       if constexpr (MODE == 2) {
 #pragma unroll
         for (int d = 0; d <= HN; ++d) {
           const int b = a + d < NEN ? a + d : a + d - NEN;
-          const double h0 = sG[q][b][0][le], h1 = sG[q][b][1][le], h2 = sG[q][b][2][le];
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk) acc[3 * d + kk] += T[3 * kk] * h0 + T[3 * kk + 1] * h1 + T[3 * kk + 2] * h2;
+          add_block(3 * d, sG[q][b][0][le], sG[q][b][1][le], sG[q][b][2][le]);
         }
       } else {
 #pragma unroll
-        for (int b = 0; b < NEN; ++b) {
-          const double h0 = sG[q][b][0][le], h1 = sG[q][b][1][le], h2 = sG[q][b][2][le];
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk) acc[3 * b + kk] += T[3 * kk] * h0 + T[3 * kk + 1] * h1 + T[3 * kk + 2] * h2;
-        }
+        for (int b = 0; b < NEN; ++b) add_block(3 * b, sG[q][b][0][le], sG[q][b][1][le], sG[q][b][2][le]);
       }
     }
   };
