@@ -309,7 +309,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
-    ap.add_argument("--cpu-sample", type=int, default=4096, help="elements in the oracle CPU sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=12288, help="elements in the oracle CPU sample (0: skip)")
     ap.add_argument("--assembly", default="gather", choices=["gather", "coloured", "tables"],
                     help="gather: element-major tables + one pass per node (default); coloured: element rows "
                          "scattered into CSR colour by colour; tables: element tables + coloured assembly")
