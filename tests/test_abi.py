@@ -170,3 +170,20 @@ def test_model_kinds_sizes_and_errors(lib):
     dummy = C.c_void_p(1)
     rc = lib.pa_param_backward(C.byref(d), dummy, L.PA_FP64, 0, None, None, dummy, dummy, 1 << 20, None)
     assert rc == L.PA_ERR_UNSUPPORTED
+
+
+def test_empty_mesh_is_a_no_op(lib):
+    """An empty mesh returns PA_OK from the tangent builds before any launch
+    (no GPU needed), once the argument checks have passed."""
+    d = _desc()
+    m = L.Mesh(0, 8, 8, 8, None, None, None, None)
+    inc = L.Incidence(8, 0, 81, 8, None)
+    csr = L.Csr(24, 0, 8, 8, 8)
+    rc = lib.pa_tangent_build_gather(C.byref(d), None, 0, C.byref(m), C.byref(inc), C.byref(csr), None,
+                                     C.c_void_p(8), C.c_void_p(8), None, None, 0, None)
+    assert rc == L.PA_OK, lib.pa_last_error()
+    # the node and CSR arrays are still required
+    csr = L.Csr(24, 0, None, 8, None)
+    rc = lib.pa_tangent_build_gather(C.byref(d), None, 0, C.byref(m), C.byref(inc), C.byref(csr), None,
+                                     C.c_void_p(8), C.c_void_p(8), None, None, 0, None)
+    assert rc == L.PA_ERR_ARG

@@ -177,3 +177,34 @@ def test_inline_geometry_matches_stored(kind, n):
     rg, Kg = fe.assemble(cperm, r_ref, K_ref, X.shape[0])
     close(r1.cpu().numpy(), rg, 1e-12, "r")
     close(v1.cpu().numpy(), Kg.data, 1e-12, "vals")
+
+
+@pytest.mark.parametrize("kind", ["hex8", "tet10"])
+def test_single_cube_and_orphan_node(kind):
+    """Edge cases of the element and assembly path: one hex8 element (every
+    node on the boundary, one partially filled workgroup) or one Kuhn cube
+    of six tet10 elements, plus a node that no element references (its CSR
+    rows are empty and its residual entries must come out as zero)."""
+    api = need_gpu()
+    say("single cube + orphan node", kind)
+    X, conn, par = (synth.hex_mesh if kind == "hex8" else synth.tet10_mesh)(1)
+    X = np.vstack([X, [[2.0, 2.0, 2.0]]])  # unreferenced node
+    u = synth.displacement_uniform(X.shape[0], 0.05, seed=0)
+    p = synth.num_inputs(2)
+    theta = synth.micnn_params(p, 16, 2, seed=1)
+    Av = synth.structural_vectors(2)
+    gm = api.Model(theta, 2, 16, 2, A=Av, normalize=True, algorithm="adjoint")
+    om = ncm.model_from_theta(theta, p, 16, 2, Av, normalize=True)
+    mesh = api.FEMesh(X, conn, colour=par)
+    cperm = conn[mesh.perm]
+    dNdX, w, _ = fe.geometry(X, cperm)
+    r_ref, K_ref, _ = fe.element_residual_stiffness(u, cperm, dNdX, w, om)
+    rg, Kg = fe.assemble(cperm, r_ref, K_ref, X.shape[0])
+    ut = torch.tensor(u, device="cuda")
+    for assembly in ("gather", "coloured"):
+        r, vals = api.tangent_build(gm, mesh, ut, prec="fp64", assembly=assembly)
+        close(r.cpu().numpy(), rg, 1e-12, f"r ({assembly})")
+        close(vals.cpu().numpy(), Kg.data, 1e-12, f"vals ({assembly})")
+        assert np.all(r.cpu().numpy()[-3:] == 0.0)
+    r_e, K_e = api.element_residual_stiffness(gm, mesh, ut, prec="fp64")
+    close(K_e.cpu().numpy().transpose(2, 0, 1), K_ref, 1e-12, "K_e")
