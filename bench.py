@@ -435,8 +435,10 @@ def main():
 
     variants = {}
     for vp in [x for x in args.variants.split(",") if x and x not in ("none", args.prec)]:
-        # the adjoint-form Hessian has FP64 and FP32 kernels only
-        model.algorithm = args.algo if vp in ("fp64", "fp32") else "forward"
+        # the adjoint form has FP64 and FP32 kernels, and BF16 with the FP32
+        # correction for two hidden layers of width <= 32
+        adj_ok = vp in ("fp64", "fp32") or (vp == "bf16_corr" and Lh == 2 and h <= 32)
+        model.algorithm = args.algo if adj_ok else "forward"
         vms, vk = run(vp, max(args.steps // 2, 2), 1, True)
         err_r = (bufs["r"] - r_ref).norm().item() / r_ref.norm().item()
         err_K = (bufs["vals"] - v_ref).norm().item() / v_ref.norm().item()

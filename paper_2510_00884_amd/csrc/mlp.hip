@@ -1119,9 +1119,23 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     // ---- layer-2 Jacobian, one row block at a time, Gram pairs as columns form
 #pragma unroll 1
     for (int ob = 0; ob < MB; ++ob) {
-      frag_t AV[SH];
+      // PREC_BF16C: the layer-2 Jacobian contracts over the neurons on the
+      // BF16 matrix cores (16x16x32, FP32 accumulation; the K dimension of
+      // the prepared BF16 fragments is permuted to the FP32 accumulator
+      // layout, so the column sources pack without shuffles); everything
+      // else in this kernel is FP32
+      constexpr bool JB = PR == PREC_BF16C;
+      constexpr int SHB = (H + 31) / 32;
+      frag_t AV[JB ? 1 : SH];
+      bf16x8 AZ[JB ? SHB : 1];
+      if constexpr (JB) {
+        const bf16x8* zA = frag_ptr<EngBF16>(prep, lay, 1);
 #pragma unroll
-      for (int s = 0; s < SH; ++s) AV[s] = fA[(ob * SH + s) * 64 + lane];
+        for (int s = 0; s < SHB; ++s) AZ[s] = zA[((1 * MB + ob) * SHB + s) * 64 + lane];
+      } else {
+#pragma unroll
+        for (int s = 0; s < SH; ++s) AV[s] = fA[(ob * SH + s) * 64 + lane];
+      }
       T g2[4];  // gamma_2 of row block ob, selected without indexing registers at run time
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -1171,7 +1185,11 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) src[mb][v] = s1[mb][v] * W1s[m][16 * mb + E::row(g, v) + zr];
-        const acc_t acc = mma_src<E, MB>(AV, src, zero_acc<E>());
+        acc_t acc;
+        if constexpr (JB)
+          acc = mma_src<EngBF16, MB>(AZ, src, zero_acc<EngBF16>());
+        else
+          acc = mma_src<E, MB>(AV, src, zero_acc<E>());
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           Jc[v] = (T)acc[v] + B2s[m][16 * ob + E::row(g, v)];
@@ -1304,6 +1322,10 @@ static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char
         return 0;
       case PREC_F32:
         if (hess) launch_adj2_one<H, P, PREC_F32, true>(lay, prep, n, K, out, s);
+        else launch_adj2_one<H, P, PREC_F32, false>(lay, prep, n, K, out, s);
+        return 0;
+      case PREC_BF16C:  // FP32 value and gradient, layer-2 Jacobian in BF16
+        if (hess) launch_adj2_one<H, P, PREC_BF16C, true>(lay, prep, n, K, out, s);
         else launch_adj2_one<H, P, PREC_F32, false>(lay, prep, n, K, out, s);
         return 0;
       default: return -2;
