@@ -181,8 +181,8 @@ def other_workload(args):
         F = torch.tensor(synth.sample_F(n, seed=0), device="cuda")
         res = {}
         ref = None
-        for prec, algo in [("fp64", "adjoint"), ("fp32", "adjoint"), ("bf16", "forward"), ("bf16_corr", "forward"),
-                           ("fp64", "forward")]:
+        for prec, algo in [("fp64", "adjoint"), ("fp32", "adjoint"), ("bf16_corr", "adjoint"), ("bf16", "forward"),
+                           ("bf16_corr", "forward"), ("fp64", "forward")]:
             gm = api.Model(theta, n_sv, h, Lh, A=Av, normalize=True, algorithm=algo)
             bufs = {}
             def call():
@@ -435,10 +435,8 @@ def main():
 
     variants = {}
     for vp in [x for x in args.variants.split(",") if x and x not in ("none", args.prec)]:
-        # the adjoint form has FP64 and FP32 kernels, and BF16 with the FP32
-        # correction for two hidden layers of width <= 32
-        adj_ok = vp in ("fp64", "fp32") or (vp == "bf16_corr" and Lh == 2 and h <= 32)
-        model.algorithm = args.algo if adj_ok else "forward"
+        # the adjoint form has FP64, FP32 and BF16-with-FP32-correction kernels
+        model.algorithm = args.algo if vp in ("fp64", "fp32", "bf16_corr") else "forward"
         vms, vk = run(vp, max(args.steps // 2, 2), 1, True)
         err_r = (bufs["r"] - r_ref).norm().item() / r_ref.norm().item()
         err_K = (bufs["vals"] - v_ref).norm().item() / v_ref.norm().item()

@@ -65,12 +65,11 @@ typedef enum {
                           gradient and Hessian columns carried layer by layer */
   PA_ALGO_ADJOINT = 1  /* value forward, value adjoint backward, then the
                           Jacobian forward accumulating the Hessian as
-                          sum_k J_k^T diag(lambda_k F''(y_k)) J_k; FP64 and
-                          FP32; PA_BF16_CORR for two hidden layers of width
-                          <= 32 (value, gradient and the layer-1 term in
-                          FP32, the layer-2 Jacobian on the BF16 matrix
-                          cores with FP32 accumulation); other BF16 cases
-                          return PA_ERR_UNSUPPORTED                          */
+                          sum_k J_k^T diag(lambda_k F''(y_k)) J_k; FP64,
+                          FP32 and PA_BF16_CORR (value, gradient, reverse
+                          sweep and layer-1 term in FP32, the Jacobians of
+                          layers >= 2 on the BF16 matrix cores with FP32
+                          accumulation); PA_BF16: PA_ERR_UNSUPPORTED         */
 } pa_algorithm;
 
 typedef enum { PA_ACT_SOFTPLUS = 0 } pa_activation;

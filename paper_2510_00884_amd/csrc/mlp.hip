@@ -678,6 +678,25 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 #pragma unroll
     for (int s = 0; s < S1; ++s) BV[k - 2][s] = fB[(((k - 1) * MB + w) * S1 + s) * 64 + lane];
   }
+  // PREC_BF16C: the Jacobian pass of layers >= 2 runs on the BF16 matrix
+  // cores (these fragments, K permuted to the FP32 accumulator layout);
+  // value, reverse sweep, gradient and the layer-1 Gram stay FP32
+  constexpr bool JB = PR == PREC_BF16C;
+  constexpr int SHB = (H + 31) / 32;
+  bf16x8 AZ[JB ? L - 1 : 1][JB ? SHB : 1];
+  if constexpr (JB && HESS) {
+    const bf16x8* zA = frag_ptr<EngBF16>(prep, lay, 1);
+#pragma unroll
+    for (int k = 2; k <= L; ++k)
+#pragma unroll
+      for (int s = 0; s < SHB; ++s) AZ[k - 2][s] = zA[(((k - 1) * MB + w) * SHB + s) * 64 + lane];
+  }
+  auto jac_product = [&](int kk, const T (&src)[MB][4]) -> acc_t {
+    if constexpr (JB)
+      return mma_src<EngBF16, MB>(AZ[kk], src, zero_acc<EngBF16>());
+    else
+      return mma_src<E, MB>(AV[kk], src, zero_acc<E>());
+  };
   for (int i = tid; i < L * H; i += 64 * NW) (&cs[0][0])[i] = t_c[i];
   for (int i = tid; i < H; i += 64 * NW) as_[i] = t_a[i];
   __syncthreads();  // W1s, Bs, cs, as_
@@ -860,7 +879,7 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
                 const int r = 16 * mb + E::row(g, v);
                 src[mb][v] = l1buf[1][r][q] * W1s[m][r];
               }
-            acc_t acc = mma_src<E, MB>(AV[0], src, zero_acc<E>());
+            acc_t acc = jac_product(0, src);
 #pragma unroll
             for (int v = 0; v < 4; ++v) J[m][v] = (T)acc[v] + Bs[0][m][16 * w + E::row(g, v)];
             static_for<m + 1>([&](auto NI) {
@@ -888,7 +907,7 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
                 for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                   for (int v = 0; v < 4; ++v) src[mb][v] = xbuf[m - c0][16 * mb + E::row(g, v)][q];
-                acc_t acc = mma_src<E, MB>(AV[k - 2], src, zero_acc<E>());
+                acc_t acc = jac_product(k - 2, src);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) J[m][v] = (T)acc[v] + Bs[k - 2][m][16 * w + E::row(g, v)];
               }
@@ -1338,6 +1357,10 @@ static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char
       break;
     case PREC_F32:
       if (hess) launch_adj_one<H, L, P, PREC_F32, true>(lay, prep, n, K, out, s);
+      else launch_adj_one<H, L, P, PREC_F32, false>(lay, prep, n, K, out, s);
+      break;
+    case PREC_BF16C:  // FP32 value and gradient, Jacobian pass in BF16
+      if (hess) launch_adj_one<H, L, P, PREC_BF16C, true>(lay, prep, n, K, out, s);
       else launch_adj_one<H, L, P, PREC_F32, false>(lay, prep, n, K, out, s);
       break;
     default: return -2;
