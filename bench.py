@@ -274,10 +274,16 @@ def other_workload(args):
         ws = torch.empty(mesh.workspace_bytes(gm, "gather"), dtype=torch.uint8, device="cuda")
         bufs = {}
         res = {}
-        for prec in ("fp32", "fp64"):
+        ref = None
+        for prec in ("fp64", "fp32", "bf16_corr"):
             ms, kern = _profiled(lib, lambda: api.tangent_build(gm, mesh, u, prec=prec, workspace=ws, bufs=bufs),
                                  steps, warmup)
             res[prec] = {"ms": ms, "qp_per_s": mesh.n_el * mesh.nq / (ms / 1e3), "kernels_ms": kern}
+            if ref is None:
+                ref = (bufs["r"].clone(), bufs["vals"].clone())
+            else:
+                res[prec]["rel_err_vs_fp64_r"] = ((bufs["r"] - ref[0]).norm() / ref[0].norm()).item()
+                res[prec]["rel_err_vs_fp64_K"] = ((bufs["vals"] - ref[1]).norm() / ref[1].norm()).item()
             print(f"[bench] tet10 {prec}: {ms:.3f} ms", file=sys.stderr, flush=True)
         ms = res["fp32"]["ms"]
         line = {"metric": "qp evals/s (Psi+P+tangent) & elements assembled/s, FP64 vs FP32/BF16 at stated error",
