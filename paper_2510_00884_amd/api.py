@@ -65,7 +65,9 @@ class Model:
     def __init__(self, theta, n_sv, width=16, n_hidden=2, A=None, normalize=False, has_bias=True,
                  algorithm="forward", device="cuda", kind="micnn"):
         """kind: "micnn" (eq. icnn), "cann" (App. B.1) or "gent_thomas" (eq. gt);
-        width and n_hidden apply to the MICNN only."""
+        width (1..16, 32 or 64) and n_hidden (2..4) apply to the MICNN only.
+        algorithm: "forward" (Alg. 4; 2-3 hidden layers, every precision) or
+        "adjoint" (adjoint-form Hessian; FP64, FP32 and "bf16_corr")."""
         self.lib = L.load()
         self.desc = _desc(n_sv, width, n_hidden, A, normalize, has_bias, algorithm, kind)
         self.n_sv, self.width, self.n_hidden = int(n_sv), int(width), int(n_hidden)
