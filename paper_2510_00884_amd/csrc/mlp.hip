@@ -632,7 +632,7 @@ __host__ __device__ constexpr int colmaj_n(int t) { return t - colmaj_m(t) * (co
 // Packed row-major index of pair (n, m), n <= m.
 __host__ __device__ constexpr int packed_index(int n, int m, int P) { return n * P - n * (n - 1) / 2 + (m - n); }
 
-template <int H, int L, int P, int PR, bool HESS>
+template <int H, int L, int P, int PR, bool HESS, bool PERSIST = !HESS>
 __global__ void __launch_bounds__(64 * (H / 16))
 k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
           const double* __restrict__ Kin, double* __restrict__ out) {
@@ -943,10 +943,15 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     }
     __syncthreads();  // outp, l1buf and xbuf free for the next tile
   };
-  if constexpr (HESS) {
+  if constexpr (!PERSIST) {
     tile_body(blockIdx.x);  // one tile per workgroup (see the launcher)
   } else {
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) tile_body(tile);
+    // block-uniform tile loop: every wave of a workgroup runs the same
+    // tiles, so the barriers inside tile_body match
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+      asm volatile("" ::: "memory");
+      tile_body(tile);
+    }
   }
 }
 
@@ -1311,15 +1316,45 @@ static unsigned persistent_grid(K kernel, int block, int64_t ntiles) {
   return (unsigned)(ntiles < cached_cap ? ntiles : cached_cap);
 }
 
+// Workgroups of a kernel that fit on one CU at once (cached per kernel and device).
+template <class K>
+static int blocks_per_cu(K kernel, int block) {
+  static thread_local const void* cached_k = nullptr;
+  static thread_local int cached_dev = -1, cached = 0;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (cached_k != (const void*)kernel || cached_dev != dev) {
+    int per_cu = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
+    cached = per_cu;
+    cached_k = (const void*)kernel;
+    cached_dev = dev;
+  }
+  return cached;
+}
+
 template <int H, int L, int P, int PR, bool HESS>
 static void launch_adj_one(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
                            double* out, hipStream_t s) {
   const int block = 64 * (H / 16);
-  // with the Hessian the per-tile state leaves no registers for keeping the
-  // weight fragments across tiles: one tile per workgroup
   const int64_t ntiles = (n + 15) / 16;
-  const unsigned grid = HESS ? (unsigned)ntiles : persistent_grid(k_mlp_adj<H, L, P, PR, HESS>, block, ntiles);
-  k_mlp_adj<H, L, P, PR, HESS><<<grid, block, 0, s>>>(prep, lay, n, K, out);
+  if constexpr (!HESS) {
+    k_mlp_adj<H, L, P, PR, false><<<persistent_grid(k_mlp_adj<H, L, P, PR, false>, block, ntiles), block, 0, s>>>(
+        prep, lay, n, K, out);
+  } else {
+    // With the Hessian a tile loop keeps values live across tiles and costs
+    // occupancy, so a workgroup takes one tile; only where that kernel fits a
+    // single workgroup per CU anyway (FP64, large networks) are the
+    // workgroups persistent, staging the weights once.
+    if constexpr (PR == PREC_F64) {
+      if (blocks_per_cu(k_mlp_adj<H, L, P, PR, true, false>, block) <= 1) {
+        k_mlp_adj<H, L, P, PR, true, true><<<persistent_grid(k_mlp_adj<H, L, P, PR, true, true>, block, ntiles),
+                                             block, 0, s>>>(prep, lay, n, K, out);
+        return;
+      }
+    }
+    k_mlp_adj<H, L, P, PR, true, false><<<(unsigned)ntiles, block, 0, s>>>(prep, lay, n, K, out);
+  }
 }
 
 template <int H, int P, int PR, bool HESS>
