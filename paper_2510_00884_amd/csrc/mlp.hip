@@ -949,7 +949,8 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     // block-uniform tile loop: every wave of a workgroup runs the same
     // tiles, so the barriers inside tile_body match
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-      asm volatile("" ::: "memory");
+      // with the Hessian, nothing read in the tile body stays live across tiles
+      if constexpr (HESS) asm volatile("" ::: "memory");
       tile_body(tile);
     }
   }
