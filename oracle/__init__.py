@@ -9,8 +9,9 @@ code with the GPU path.  It evaluates the plain definitions, vectorised over
 quadrature points with NumPy, in the paper's order:
 
 * ``ncm``      kinematic layer (invariants, App. A.2.1-A.2.2; training features,
-               App. C), inner network evaluated by the one-pass algorithm
-               (Alg. 4, eq. icnn), stress and stiffness by the push-forward route
+               App. C), inner network of eq. icnn with its input gradient (reverse
+               sweep) and input Hessian (Hessian-vector products), stress and
+               stiffness by the push-forward route
                (eqs. stress-cgo, stiffnes-cgo, second-and-fourth) pulled back to
                P and dP/dF (App. A.1).
 * ``fe``       isoparametric hex8 / tet10 elements, Gauss quadrature, element

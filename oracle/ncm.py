@@ -153,40 +153,84 @@ def _sigmoid(y):
 
 
 # ----------------------------------------------------------------------------
-# Inner network: (M)ICNN, one-pass value + gradient + Hessian (Alg. 4)
+# Inner network: (M)ICNN value, input gradient and input Hessian (eq. icnn)
 # ----------------------------------------------------------------------------
 def micnn(K, hidden, a, b):
-    """Alg. 4 of App. B.2.
+    """Value, input gradient and input Hessian of the network of eq. (icnn).
 
     ``hidden`` = [(W1, None, c1), (A2, B2, c2), ...]; ``a``, ``b`` output weights.
     K: (n, p).  Returns N (n,), dN (n, p), d2N (n, p, p).
+
+    The derivatives are the plain chain and product rules applied to the layer
+    recursion y_k = A_k z_{k-1} + B_k K + c_k, z_k = F(y_k), z_0 = K,
+    N = a.z_L + b.K, organised as
+      gradient: the reverse sweep lambda_L = a, mu_k = lambda_k * F'(y_k),
+                lambda_{k-1} = A_k^T mu_k, dN/dK = b + sum_k B_k^T mu_k + lambda_0;
+      Hessian:  column m is the derivative of that reverse sweep along the
+                input direction e_m (tangents ydot_k of the layer recursion,
+                then mudot_k = lambdadot_k * F'(y_k) + lambda_k * F''(y_k) * ydot_k,
+                lambdadot_{k-1} = A_k^T mudot_k), i.e. one Hessian-vector
+                product per input.
+    The App. B.2 algorithm computes the same quantities by carrying the
+    second-derivative columns forward instead; the complex-step and
+    closed-form pins in the tests check these against the plain value pass.
     """
     n, p = K.shape
+    # forward: pre-activations of every layer
+    ys = []
     z = K
-    dz = np.broadcast_to(np.eye(p), (n, p, p))
-    d2z = np.zeros((n, p, p, p), dtype=K.dtype)
     for (A, B, c) in hidden:
-        y = np.einsum("jk,nk->nj", A, z) + c
-        dy = np.einsum("jk,nkm->njm", A, dz)
+        y = z @ A.T + c
         if B is not None:
-            y = y + np.einsum("jk,nk->nj", B, K)
-            dy = dy + B[None]
-        d2y = np.einsum("jk,nkmo->njmo", A, d2z)
-        f0 = _softplus(y)
-        s = _sigmoid(y)
-        f1 = s
-        f2 = s * (1.0 - s)
-        d2z = f1[:, :, None, None] * d2y + f2[:, :, None, None] * dy[:, :, :, None] * dy[:, :, None, :]
-        dz = f1[:, :, None] * dy
-        z = f0
+            y = y + K @ B.T
+        ys.append(y)
+        z = _softplus(y)
     N = z @ a + K @ b
-    dN = np.einsum("j,njm->nm", a, dz) + b
-    d2N = np.einsum("j,njmo->nmo", a, d2z)
+    s1 = [_sigmoid(y) for y in ys]          # F'(y_k)
+    s2 = [s * (1.0 - s) for s in s1]        # F''(y_k)
+    # reverse sweep (gradient)
+    Lh = len(hidden)
+    lams = [None] * Lh                      # lambda_k = dN/dz_k
+    mus = [None] * Lh
+    lam = np.broadcast_to(a, ys[-1].shape)
+    dN = np.broadcast_to(b, (n, p)).astype(np.result_type(K, a, b)).copy()
+    for k in range(Lh - 1, -1, -1):
+        A, B, _ = hidden[k]
+        lams[k] = lam
+        mu = lam * s1[k]
+        mus[k] = mu
+        if B is not None:
+            dN = dN + mu @ B
+        lam = mu @ A                        # lambda_{k-1}; lambda_0 = dN/dz_0 through z_0 = K
+    dN = dN + lam
+    # tangent of the reverse sweep along every input direction (Hessian columns)
+    d2N = np.zeros((n, p, p), dtype=dN.dtype)
+    for m in range(p):
+        e = np.zeros(p)
+        e[m] = 1.0
+        ydots = []
+        zdot = np.broadcast_to(e, (n, p))
+        for (A, B, _), s in zip(hidden, s1):
+            yd = zdot @ A.T
+            if B is not None:
+                yd = yd + B @ e
+            ydots.append(yd)
+            zdot = s * yd
+        col = np.zeros((n, p), dtype=dN.dtype)
+        lamdot = np.zeros_like(ys[-1])
+        for k in range(Lh - 1, -1, -1):
+            A, B, _ = hidden[k]
+            mudot = lamdot * s1[k] + lams[k] * s2[k] * ydots[k]
+            if B is not None:
+                col = col + mudot @ B
+            lamdot = mudot @ A
+        d2N[:, :, m] = col + lamdot
     return N, dN, d2N
 
 
 def micnn_value(K, hidden, a, b):
-    """Plain forward pass of eq. (icnn) (value only); used to pin Alg. 4."""
+    """Plain forward pass of eq. (icnn) (value only); the derivatives of
+    ``micnn`` are pinned against it by complex steps."""
     z = K
     for (A, B, c) in hidden:
         y = np.einsum("jk,nk->nj", A, z) + c

@@ -87,7 +87,7 @@ def test_invariants_closed_form_diagonal():
     assert np.isclose(K[6], l2[0] ** 2 * J ** (2 * ex["I5"]) - 1)
 
 
-# ---------------------------------------------------------------- Alg. 4
+# ---------------------------------------------------------------- network derivatives (eq. icnn)
 def test_single_unit_closed_form():
     """N = a softplus(w.K + c) + b.K has closed-form gradient and Hessian."""
     r = np.random.default_rng(3)
@@ -103,7 +103,7 @@ def test_single_unit_closed_form():
 
 
 @pytest.mark.parametrize("n_sv,h,L", [(0, 6, 2), (1, 16, 2), (2, 8, 3), (2, 4, 4)])
-def test_alg4_derivatives_by_complex_step(n_sv, h, L):
+def test_network_derivatives_by_complex_step(n_sv, h, L):
     m = make_model(n_sv, h, L)
     p = m.p
     K = np.random.default_rng(5).normal(scale=0.4, size=(11, p))
