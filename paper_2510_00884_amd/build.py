@@ -13,7 +13,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpa.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mlp.hip", "adjoint.hip", "kin_chain.hip", "fe.hip", "closed.hip", "api.cpp", "host_setup.cpp"]
+SOURCES = ["mlp_adj_h64.hip", "mlp_adj_h32.hip", "mlp_fwd_h64.hip", "mlp_adj_h16.hip", "mlp_fwd_h32.hip",
+           "mlp_fwd_h16.hip", "mlp.hip", "adjoint.hip", "kin_chain.hip", "fe.hip", "closed.hip", "api.cpp", "host_setup.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", CSRC, "-I", INCLUDE,
           "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -32,7 +33,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 8)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

@@ -89,6 +89,17 @@ int launch_prepare(const PrepLayout& lay, const ThetaLayout& tl, const double* t
                    unsigned char* prep, int normalize, int npair, hipStream_t s);
 int launch_mlp(const PrepLayout& lay, int prec, int algo, const unsigned char* prep, int64_t n,
                const double* K, double* out, int hess, hipStream_t s);
+// per-width instantiations (mlp_fwd_h*.hip, mlp_adj_h*.hip)
+#define PA_MLP_LAUNCHER(name)                                                                                 \
+  int name(const PrepLayout& lay, int prec, const unsigned char* prep, int64_t n, const double* K, double* out, \
+           int hess, hipStream_t s);
+PA_MLP_LAUNCHER(launch_mlp_fwd_h16)
+PA_MLP_LAUNCHER(launch_mlp_fwd_h32)
+PA_MLP_LAUNCHER(launch_mlp_fwd_h64)
+PA_MLP_LAUNCHER(launch_mlp_adj_h16)
+PA_MLP_LAUNCHER(launch_mlp_adj_h32)
+PA_MLP_LAUNCHER(launch_mlp_adj_h64)
+#undef PA_MLP_LAUNCHER
 
 // parameter adjoint (adjoint.hip)
 int64_t param_backward_ws(int H, int L, int P, int prec, int64_t n);
