@@ -304,10 +304,19 @@ int pa_tangent_build_gather(const pa_model_desc* desc, const void* prepared, int
 size_t pa_param_backward_workspace(const pa_model_desc* desc, int prec, int64_t n_qp);
 /* Parameter adjoint of the stress (raw network, normalize must be 0):
  *   theta_bar = sum_q (dP_q/dtheta)^T P_bar_q
- * with P_q = sum_m dN/dK_m(K_q; theta) dK_m/dF(F_q).  Activations are
- * recomputed, not stored.  F, P_bar: [9][n_qp]; theta_bar [n_params] is
- * overwritten (FP64; the reduction over points is in a fixed order).
- * prec: PA_FP64 or PA_FP32. */
+ * with P_q = sum_m dN/dK_m(K_q; theta) dK_m/dF(F_q), the stress of the chain
+ * rule of eq. nncm-chain with N the network of eq. icnn (App. B.2).  This is
+ * the reverse-mode derivative, in the parameters, of the first-derivative
+ * part of the App. B.2 network evaluation (the gradient columns of Alg. 4),
+ * contracted with lambda_q,m = P_bar_q : dK_m/dF: the gradient of a
+ * stress-calibration loss such as mean ||P - P_target||^2 (P_bar = dLoss/dP),
+ * which is how the paper's NCMs are fitted to stress data.  Activations are
+ * recomputed, not stored.  F, P_bar: [9][n_qp] (caller-owned, read only);
+ * theta_bar [n_params] is overwritten (FP64; the reduction over points is in
+ * a fixed order, so the result is bitwise reproducible).  prec: PA_FP64 or
+ * PA_FP32 (others: PA_ERR_UNSUPPORTED).  workspace:
+ * pa_param_backward_workspace bytes (features, lambda and per-workgroup
+ * partial gradients), else PA_ERR_WORKSPACE. */
 int pa_param_backward(const pa_model_desc* desc, const void* prepared, int prec, int64_t n_qp,
                       const double* F, const double* P_bar, double* theta_bar,
                       void* workspace, size_t ws_bytes, void* stream);
@@ -319,7 +328,9 @@ int pa_param_backward(const pa_model_desc* desc, const void* prepared, int prec,
  *   r_bar_d = dL/dr_d = 2 r_d (free), -2 (R_b - sum_{boundary b} r) (d on b).
  * r [n_rows]: assembled residual (node-major dofs); dof_group [n_rows] int32:
  * -1 = free (D^free), b in [0, n_groups) = constrained dof of reaction
- * boundary b (D^fix_b), -2 = constrained and not observed.  R: device
+ * boundary b (D^fix_b), -2 = constrained and not observed; any other value is
+ * treated as -2 (no loss term, zero cotangent; the ids are device data, so
+ * the library cannot refuse them without a synchronisation).  R: device
  * [n_groups] reaction forces.  loss: device [1] or NULL; r_bar [n_rows] or
  * NULL.  The sums are reduced in a fixed order (bitwise reproducible).
  * n_groups <= 63.  Over several time steps, sum the losses and the

@@ -22,6 +22,26 @@ def _p(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _need(t, name, numel, dtype=torch.float64, device=None):
+    """Checks, before anything is launched, that a tensor handed to the
+    library has the element type, device and size the C entry point reads or
+    writes (a wrong one would make a kernel read or write past its end)."""
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (got device {t.device})")
+    if device is not None and t.device != torch.device(device):
+        raise ValueError(f"{name} is on {t.device}, the model is on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, {numel} expected")
+
+
 def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -76,17 +96,46 @@ class Model:
         if not self.lib.pa_supported(C.byref(self.desc)):
             raise L.PaError(f"unsupported model: {self.lib.pa_last_error().decode()}")
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self._key = None
         self.set_params(theta)
+
+    def _prepare(self, th):
+        nb = self.lib.pa_prepared_bytes(C.byref(self.desc))
+        prepared = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        _need(th, "theta", self.n_params, device=self.device)
+        L.check(self.lib.pa_prepare_params(C.byref(self.desc), _p(th), _p(prepared), _stream()),
+                "pa_prepare_params")
+        return prepared
 
     def set_params(self, theta):
         th = torch.as_tensor(theta, dtype=torch.float64, device=self.device).contiguous().reshape(-1)
         if th.numel() != self.n_params:
             raise ValueError(f"theta has {th.numel()} entries, model needs {self.n_params}")
         self.theta = th
-        nb = self.lib.pa_prepared_bytes(C.byref(self.desc))
-        self.prepared = torch.empty(nb, dtype=torch.uint8, device=self.device)
-        L.check(self.lib.pa_prepare_params(C.byref(self.desc), _p(self.theta), _p(self.prepared), _stream()),
-                "pa_prepare_params")
+        self.prepared = self._prepare(th)
+        self._key = (th.data_ptr(), th._version)
+
+    def prepared_for(self, theta):
+        """Prepared buffer of this parameter tensor: the model's own when
+        theta is the tensor it last prepared and has not been modified since,
+        otherwise a new buffer prepared from theta (the model keeps it, so a
+        later call with the same unmodified tensor reuses it).  The returned
+        buffer is never written again, so a caller may hold on to it (the
+        autograd Function keeps the one its forward used for its backward)."""
+        th = theta.detach()
+        if th.dtype != torch.float64 or th.device != self.device or not th.is_contiguous():
+            th = th.to(device=self.device, dtype=torch.float64).contiguous()
+        th = th.reshape(-1)
+        if th.numel() != self.n_params:
+            raise ValueError(f"theta has {th.numel()} entries, model needs {self.n_params}")
+        key = (theta.data_ptr(), theta._version)
+        if key != self._key:
+            self.theta = th
+            self.prepared = self._prepare(th)
+            self._key = key
+        return self.prepared
 
     @property
     def algorithm(self):
@@ -114,6 +163,7 @@ def invariants(model: Model, F, soa: bool = False):
     """I_raw (4 + 2 npair, n), K (p, n), dKdF (p, 9, n)."""
     Fs = F if soa else _soa9(F)
     n = Fs.shape[1]
+    _need(Fs, "F", 9 * n, device=model.device)
     npair = model.n_sv * (model.n_sv + 1) // 2
     I_raw = torch.empty((4 + 2 * npair, n), dtype=torch.float64, device=Fs.device)
     K = torch.empty((model.p, n), dtype=torch.float64, device=Fs.device)
@@ -124,12 +174,14 @@ def invariants(model: Model, F, soa: bool = False):
 
 
 def energy_stress_tangent(model: Model, F, prec="fp64", psi=True, P=True, A=True, soa=False,
-                          n_bad=None, workspace=None, out=None):
+                          n_bad=None, workspace=None, out=None, prepared=None):
     """Psi (n,), P (9, n), AA (81, n) in SoA layout (as returned by the
-    library).  ``F`` is (n, 3, 3) or, with soa=True, (9, n)."""
+    library).  ``F`` is (n, 3, 3) or, with soa=True, (9, n).  ``prepared``:
+    a prepared-parameter buffer of this model (default: the model's own)."""
     Fs = F if soa else _soa9(F)
     n = Fs.shape[1]
     dev = Fs.device
+    _need(Fs, "F", 9 * n, device=model.device)
     if out is None:
         out = {}
         if psi:
@@ -138,11 +190,16 @@ def energy_stress_tangent(model: Model, F, prec="fp64", psi=True, P=True, A=True
             out["P"] = torch.empty((9, n), dtype=torch.float64, device=dev)
         if A:
             out["A"] = torch.empty((81, n), dtype=torch.float64, device=dev)
+    _need(out.get("psi"), "psi", n, device=model.device)
+    _need(out.get("P"), "P", 9 * n, device=model.device)
+    _need(out.get("A"), "A", 81 * n, device=model.device)
+    _need(n_bad, "n_bad", 1, torch.int32, device=model.device)
     ws_bytes = model.lib.pa_material_workspace_bytes(C.byref(model.desc), n)
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    prep = model.prepared if prepared is None else prepared
     L.check(model.lib.pa_energy_stress_tangent(
-        C.byref(model.desc), _p(model.prepared), _prec(prec), n, _p(Fs), _p(out.get("psi")), _p(out.get("P")),
+        C.byref(model.desc), _p(prep), _prec(prec), n, _p(Fs), _p(out.get("psi")), _p(out.get("P")),
         _p(out.get("A")), _p(n_bad), _p(workspace), workspace.numel(), _stream()), "pa_energy_stress_tangent")
     return out
 
@@ -155,6 +212,7 @@ def energy_stress_tangent_voigt(model: Model, F, prec="fp64", psi=True, tau=True
     Fs = F if soa else _soa9(F)
     n = Fs.shape[1]
     dev = Fs.device
+    _need(Fs, "F", 9 * n, device=model.device)
     if out is None:
         out = {}
         if psi:
@@ -163,6 +221,10 @@ def energy_stress_tangent_voigt(model: Model, F, prec="fp64", psi=True, tau=True
             out["tau"] = torch.empty((6, n), dtype=torch.float64, device=dev)
         if cc:
             out["cc"] = torch.empty((21, n), dtype=torch.float64, device=dev)
+    _need(out.get("psi"), "psi", n, device=model.device)
+    _need(out.get("tau"), "tau", 6 * n, device=model.device)
+    _need(out.get("cc"), "cc", 21 * n, device=model.device)
+    _need(n_bad, "n_bad", 1, torch.int32, device=model.device)
     ws_bytes = model.lib.pa_material_workspace_bytes(C.byref(model.desc), n)
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
@@ -279,10 +341,14 @@ def element_residual_stiffness(model: Model, mesh: FEMesh, u, prec="fp64", stiff
     displacement, dof = 3*node + i."""
     u = u.reshape(-1).contiguous()
     dev = u.device
+    _need(u, "u", 3 * mesh.n_nodes, device=mesh.device)
     if r_e is None:
         r_e = torch.empty((mesh.nd, mesh.n_el), dtype=torch.float64, device=dev)
     if stiffness and K_e is None:
         K_e = torch.empty((mesh.nd, mesh.nd, mesh.n_el), dtype=torch.float64, device=dev)
+    _need(r_e, "r_e", mesh.nd * mesh.n_el, device=mesh.device)
+    _need(K_e if stiffness else None, "K_e", mesh.nd * mesh.nd * mesh.n_el, device=mesh.device)
+    _need(n_bad, "n_bad", 1, torch.int32, device=mesh.device)
     nb = mesh.workspace_bytes(model)
     if workspace is None or workspace.numel() < nb:
         workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
@@ -300,6 +366,10 @@ def assemble_csr(mesh: FEMesh, r_e, K_e, r=None, vals=None, zero_first=True):
         r = torch.empty(3 * mesh.n_nodes, dtype=torch.float64, device=dev)
     if vals is None and K_e is not None:
         vals = torch.empty(mesh.nnz, dtype=torch.float64, device=dev)
+    _need(r_e, "r_e", mesh.nd * mesh.n_el, device=dev)
+    _need(K_e, "K_e", mesh.nd * mesh.nd * mesh.n_el, device=dev)
+    _need(r, "r", 3 * mesh.n_nodes, device=dev)
+    _need(vals, "vals", mesh.nnz, device=dev)
     L.check(mesh.lib.pa_assemble_csr(C.byref(mesh.c_mesh), C.byref(mesh.c_col), C.byref(mesh.c_csr), _p(r_e),
                                      _p(K_e), _p(r), _p(vals), int(bool(zero_first)), _stream()), "pa_assemble_csr")
     return r, vals
@@ -331,6 +401,10 @@ def tangent_build(model: Model, mesh: FEMesh, u, prec="fp64", workspace=None, bu
         r = torch.empty(3 * mesh.n_nodes, dtype=torch.float64, device=dev)
     if vals is None:
         vals = torch.empty(mesh.nnz, dtype=torch.float64, device=dev)
+    _need(u, "u", 3 * mesh.n_nodes, device=mesh.device)
+    _need(r, "r", 3 * mesh.n_nodes, device=mesh.device)
+    _need(vals, "vals", mesh.nnz, device=mesh.device)
+    _need(n_bad, "n_bad", 1, torch.int32, device=mesh.device)
     if assembly == "gather":
         nb = mesh.workspace_bytes(model, "gather")
         if workspace is None or workspace.numel() < nb:
@@ -357,8 +431,12 @@ def residual_loss(r, dof_group, R):
     reaction boundary b, -2 constrained and unobserved; R: reaction forces."""
     lib = L.load()
     r = r.reshape(-1).contiguous()
-    grp = dof_group.to(device=r.device, dtype=torch.int32).contiguous()
+    _need(r, "r", None)
+    grp = dof_group.to(device=r.device, dtype=torch.int32).contiguous().reshape(-1)
     Rt = torch.as_tensor(R, dtype=torch.float64, device=r.device).reshape(-1).contiguous()
+    _need(grp, "dof_group", r.numel(), torch.int32, device=r.device)
+    if grp.numel() and (int(grp.min()) < -2 or int(grp.max()) >= Rt.numel()):
+        raise ValueError(f"dof_group entries must lie in [-2, {Rt.numel()}) (one group per reaction force)")
     nb = lib.pa_residual_loss_workspace(r.numel(), Rt.numel())
     ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=r.device)
     loss = torch.empty(1, dtype=torch.float64, device=r.device)
@@ -372,6 +450,8 @@ def residual_param_backward(model: Model, mesh: FEMesh, u, r_bar, prec="fp64"):
     """theta_bar = (dr/dtheta)^T r_bar for the raw network."""
     u = u.reshape(-1).contiguous()
     rb = r_bar.reshape(-1).contiguous()
+    _need(u, "u", 3 * mesh.n_nodes, device=model.device)
+    _need(rb, "r_bar", 3 * mesh.n_nodes, device=model.device)
     out = torch.empty(model.n_params, dtype=torch.float64, device=u.device)
     nb = model.lib.pa_residual_param_backward_workspace(C.byref(model.desc), C.byref(mesh.c_mesh), _prec(prec))
     ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=u.device)
@@ -390,16 +470,21 @@ def residual_loss_and_grad(model: Model, mesh: FEMesh, u, dof_group, R, prec="fp
     return loss, residual_param_backward(model, mesh, u, rbar, prec)
 
 
-def param_backward(model: Model, F, P_bar, prec="fp32", soa=False, workspace=None):
-    """theta_bar = sum_q (dP_q/dtheta)^T P_bar_q (raw network)."""
+def param_backward(model: Model, F, P_bar, prec="fp32", soa=False, workspace=None, prepared=None):
+    """theta_bar = sum_q (dP_q/dtheta)^T P_bar_q (raw network).  ``prepared``:
+    the prepared-parameter buffer of the theta to differentiate at (default:
+    the model's own)."""
     Fs = F if soa else _soa9(F)
     Pb = P_bar if soa else _soa9(P_bar)
     n = Fs.shape[1]
+    _need(Fs, "F", 9 * n, device=model.device)
+    _need(Pb, "P_bar", 9 * n, device=model.device)
     out = torch.empty(model.n_params, dtype=torch.float64, device=Fs.device)
     nb = model.lib.pa_param_backward_workspace(C.byref(model.desc), _prec(prec), n)
     if workspace is None or workspace.numel() < nb:
         workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=Fs.device)
-    L.check(model.lib.pa_param_backward(C.byref(model.desc), _p(model.prepared), _prec(prec), n, _p(Fs), _p(Pb),
+    prep = model.prepared if prepared is None else prepared
+    L.check(model.lib.pa_param_backward(C.byref(model.desc), _p(prep), _prec(prec), n, _p(Fs), _p(Pb),
                                         _p(out), _p(workspace), workspace.numel(), _stream()), "pa_param_backward")
     return out
 
@@ -407,28 +492,29 @@ def param_backward(model: Model, F, P_bar, prec="fp32", soa=False, workspace=Non
 class PaStress(torch.autograd.Function):
     """P(theta, F) with the hand-written parameter adjoint as its backward.
 
-    forward: pa_energy_stress_tangent (stress only; no Hessian columns);
-    backward: pa_param_backward (activations recomputed, nothing stored but
-    theta and F).  Gradients flow to theta only."""
+    forward: pa_energy_stress_tangent (stress only; no Hessian columns) with
+    the prepared buffer of this theta (``Model.prepared_for``: prepared once
+    per parameter version, reused while theta is unchanged);
+    backward: pa_param_backward on that same prepared buffer (activations
+    recomputed; nothing stored but theta, F and the prepared parameters), so
+    the gradient is the one of the theta the forward used even when the model
+    has since been given other parameters.  Gradients flow to theta only."""
 
     @staticmethod
     def forward(ctx, theta, F, model, prec):
-        if theta.data_ptr() != model.theta.data_ptr() or not getattr(model, "_theta_current", False):
-            model.set_params(theta.detach())
-            model._theta_current = True
-        out = energy_stress_tangent(model, F, prec=prec, psi=False, P=True, A=False)
+        prep = model.prepared_for(theta)
+        out = energy_stress_tangent(model, F, prec=prec, psi=False, P=True, A=False, prepared=prep)
         ctx.save_for_backward(theta, F)
-        ctx.model, ctx.prec = model, prec
+        ctx.model, ctx.prec, ctx.prep = model, prec, prep
         return out["P"].t().reshape(-1, 3, 3)
 
     @staticmethod
     def backward(ctx, P_bar):
         theta, F = ctx.saved_tensors
-        tb = param_backward(ctx.model, F, P_bar.contiguous(), prec=ctx.prec)
+        tb = param_backward(ctx.model, F, P_bar.contiguous(), prec=ctx.prec, prepared=ctx.prep)
         return tb.to(theta.dtype), None, None, None
 
 
 def stress(theta, F, model, prec="fp32"):
     """Differentiable first Piola-Kirchhoff stress (n, 3, 3) of the raw network."""
-    model._theta_current = False
     return PaStress.apply(theta, F, model, prec)

@@ -253,14 +253,18 @@ __global__ void __launch_bounds__(64) k_loss_finish(int nblk, int n_groups, cons
   }
 }
 
-__global__ void __launch_bounds__(256) k_loss_rbar(int64_t n_rows, const double* __restrict__ r,
+// A group id outside [-1, n_groups) is treated as constrained and unobserved
+// (as -2): it contributes nothing to the loss (k_loss_partials only matches
+// ids -1 .. n_groups-1) and gets a zero cotangent, and no R or sums entry
+// beyond n_groups is read.
+__global__ void __launch_bounds__(256) k_loss_rbar(int64_t n_rows, int n_groups, const double* __restrict__ r,
                                                    const int32_t* __restrict__ group,
                                                    const double* __restrict__ R, const double* __restrict__ sums,
                                                    double* __restrict__ rbar) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= n_rows) return;
   const int gdof = group[d];
-  rbar[d] = (gdof == -1) ? 2.0 * r[d] : (gdof >= 0) ? -2.0 * (R[gdof] - sums[1 + gdof]) : 0.0;
+  rbar[d] = (gdof == -1) ? 2.0 * r[d] : (gdof >= 0 && gdof < n_groups) ? -2.0 * (R[gdof] - sums[1 + gdof]) : 0.0;
 }
 
 // ---------------------------------------------------------------- chain rule + integration
@@ -830,7 +834,7 @@ int launch_residual_loss(int64_t n_rows, const double* r, const int32_t* group, 
   const int nb = loss_partial_blocks(n_rows);
   k_loss_partials<<<nb, LOSS_BLOCK, 0, s>>>(n_rows, r, group, n_groups, partials);
   k_loss_finish<<<1, 64, 0, s>>>(nb, n_groups, partials, R, sums, loss);
-  if (rbar && n_rows > 0) k_loss_rbar<<<nblocks(n_rows, 256), 256, 0, s>>>(n_rows, r, group, R, sums, rbar);
+  if (rbar && n_rows > 0) k_loss_rbar<<<nblocks(n_rows, 256), 256, 0, s>>>(n_rows, n_groups, r, group, R, sums, rbar);
   return 0;
 }
 

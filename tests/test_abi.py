@@ -187,3 +187,16 @@ def test_empty_mesh_is_a_no_op(lib):
     rc = lib.pa_tangent_build_gather(C.byref(d), None, 0, C.byref(m), C.byref(inc), C.byref(csr), None,
                                      C.c_void_p(8), C.c_void_p(8), None, None, 0, None)
     assert rc == L.PA_ERR_ARG
+
+
+def test_binding_argument_checks_on_host():
+    """The binding's tensor checks run on the host and refuse host memory,
+    the wrong element type and the wrong size (no GPU needed to see it)."""
+    import torch
+    from paper_2510_00884_amd import api
+    with pytest.raises(ValueError, match="GPU tensor"):
+        api._need(torch.zeros(9, dtype=torch.float64), "F", 9)
+    with pytest.raises(ValueError, match="float64"):
+        api._need(torch.zeros(9, dtype=torch.float32), "F", 9)
+    with pytest.raises(ValueError, match="int32"):
+        api._need(torch.zeros(9, dtype=torch.int64), "dof_group", 9, torch.int32)

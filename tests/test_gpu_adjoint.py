@@ -142,3 +142,61 @@ def test_residual_loss_cotangent_and_empty_groups():
     loss0, rbar0 = api.residual_loss(torch.tensor(r, device="cuda"), torch.tensor(free, device="cuda"), [])
     assert abs(loss0.item() - np.sum(r ** 2)) <= 1e-13 * np.sum(r ** 2)
     close(rbar0.cpu().numpy(), 2 * r, 1e-15, "r_bar free")
+
+
+def test_autograd_two_thetas_in_one_graph():
+    """Two stress() calls of one model with different parameters in one graph,
+    and the model given a third parameter vector before backward(): each
+    gradient is the oracle's VJP at the theta its own forward used."""
+    api = need_gpu()
+    say("autograd two thetas")
+    n_sv, h, L = 2, 16, 2
+    p = synth.num_inputs(n_sv)
+    Av = synth.structural_vectors(n_sv)
+    th1 = synth.micnn_params(p, h, L, seed=1)
+    th2 = synth.micnn_params(p, h, L, seed=4)
+    n = 300
+    F = synth.sample_F(n, seed=3)
+    W1 = synth.rng(11).normal(size=(n, 3, 3))
+    W2 = synth.rng(12).normal(size=(n, 3, 3))
+    gm = api.Model(th1, n_sv, h, L, A=Av, algorithm="adjoint")
+    Ft = torch.tensor(F, device="cuda")
+    t1 = torch.tensor(th1, device="cuda", requires_grad=True)
+    t2 = torch.tensor(th2, device="cuda", requires_grad=True)
+    P1 = api.stress(t1, Ft, gm, prec="fp64")
+    P2 = api.stress(t2, Ft, gm, prec="fp64")
+    gm.set_params(synth.micnn_params(p, h, L, seed=9))  # the model moves on before backward
+    loss = (P1 * torch.tensor(W1, device="cuda")).sum() + (P2 * torch.tensor(W2, device="cuda")).sum()
+    loss.backward()
+    ref1, Pr1 = oracle_vjp(th1, F, W1, Av, p, h, L)
+    ref2, Pr2 = oracle_vjp(th2, F, W2, Av, p, h, L)
+    close(P1.detach().cpu().numpy(), Pr1, 1e-12, "P(theta1)")
+    close(P2.detach().cpu().numpy(), Pr2, 1e-12, "P(theta2)")
+    close(t1.grad.cpu().numpy(), ref1, 1e-10, "grad theta1")
+    close(t2.grad.cpu().numpy(), ref2, 1e-10, "grad theta2")
+
+
+def test_binding_rejects_bad_tensors_before_launch():
+    """A float32, host or wrongly sized tensor is refused on the host with a
+    ValueError (nothing reaches a kernel)."""
+    api = need_gpu()
+    p = synth.num_inputs(2)
+    gm = api.Model(synth.micnn_params(p, 16, 2, seed=1), 2, 16, 2, A=synth.structural_vectors(2))
+    F = torch.tensor(synth.sample_F(64, seed=1), device="cuda")
+    for bad in (F.float(), F.cpu()):
+        with pytest.raises(ValueError):
+            api.energy_stress_tangent(gm, bad)
+        with pytest.raises(ValueError):
+            api.param_backward(gm, bad, F)
+    with pytest.raises(ValueError):
+        api.param_backward(gm, F, F[:10])
+    X, conn, par = synth.hex_mesh(2)
+    mesh = api.FEMesh(X, conn, colour=par)
+    u = torch.zeros(3 * mesh.n_nodes, device="cuda", dtype=torch.float64)
+    for bad in (u.float(), u.cpu(), u[:-3]):
+        with pytest.raises(ValueError):
+            api.tangent_build(gm, mesh, bad)
+    grp = torch.full((3 * mesh.n_nodes,), -1, dtype=torch.int32, device="cuda")
+    grp[5] = 2  # only two reaction forces below
+    with pytest.raises(ValueError):
+        api.residual_loss(u, grp, [0.0, 1.0])
