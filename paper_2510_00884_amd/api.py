@@ -22,6 +22,14 @@ def _p(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _dev(device):
+    """A device with its index filled in ("cuda" is the current device)."""
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
 def _need(t, name, numel, dtype=torch.float64, device=None):
     """Checks, before anything is launched, that a tensor handed to the
     library has the element type, device and size the C entry point reads or
@@ -34,8 +42,8 @@ def _need(t, name, numel, dtype=torch.float64, device=None):
         raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor (got device {t.device})")
-    if device is not None and t.device != torch.device(device):
-        raise ValueError(f"{name} is on {t.device}, the model is on {device}")
+    if device is not None and t.device != _dev(device):
+        raise ValueError(f"{name} is on {t.device}, the model is on {_dev(device)}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if numel is not None and t.numel() != numel:
@@ -95,9 +103,7 @@ class Model:
         self.n_params = self.lib.pa_num_params(C.byref(self.desc))
         if not self.lib.pa_supported(C.byref(self.desc)):
             raise L.PaError(f"unsupported model: {self.lib.pa_last_error().decode()}")
-        self.device = torch.device(device)
-        if self.device.type == "cuda" and self.device.index is None:
-            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.device = _dev(device)
         self._key = None
         self.set_params(theta)
 
@@ -288,7 +294,7 @@ class FEMesh:
         counts = np.bincount(colour, minlength=int(colour.max()) + 1 if n_el else 0)
         self.colour_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
         self.n_colours = len(counts)
-        dev = torch.device(device)
+        dev = _dev(device)
         self.device = dev
         self.X = torch.tensor(X.T.copy(), device=dev)
         self.conn = torch.tensor(self.conn_host.T.copy(), device=dev)
