@@ -216,6 +216,29 @@ int pa_energy_stress_tangent_voigt(const pa_model_desc* desc, const void* prepar
                                    const double* F, double* psi, double* tau, double* cc, int32_t* n_bad,
                                    void* workspace, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- no allocation */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and outputs as pa_energy_stress_tangent (same arguments, same
+ * kernels, same numbers), with the workspace taken from a device array of
+ * PA_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  Allocates nothing (no hipMalloc, hipFree or
+ * allocating library call); the caller still owns F and the outputs.  Its
+ * first call on a device looks up that device's copy of the array (with the
+ * device current).  Returns PA_ERR_WORKSPACE, launching nothing, when
+ * pa_material_workspace_bytes(desc, n_qp) exceeds the array, i.e. for
+ * n_qp > pa_noalloc_max_points(desc) (131,072 points with two structural
+ * vectors).  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind (nothing in it needs clearing: each call overwrites what
+ * it reads); calls on one stream are ordered, but calls that overlap in time
+ * on one GPU (several streams or host threads) race on the array. */
+#define PA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int pa_energy_stress_tangent_noalloc(const pa_model_desc* desc, const void* prepared, int prec,
+                                     int64_t n_qp, const double* F, double* psi, double* P,
+                                     double* AA, int32_t* n_bad, void* stream);
+/* Largest n_qp pa_energy_stress_tangent_noalloc accepts for this model. */
+int64_t pa_noalloc_max_points(const pa_model_desc* desc);
+
 /* ---------------------------------------------------------------- elements */
 /* Reference shape gradients and quadrature volumes (eqs. r-quad, k-quad):
  *   X [3][n_nodes] node coordinates, conn [nen][n_el];

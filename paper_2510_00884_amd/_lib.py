@@ -15,6 +15,7 @@ PA_OK, PA_ERR_ARG, PA_ERR_UNSUPPORTED, PA_ERR_HIP, PA_ERR_WORKSPACE = 0, -1, -2,
 PA_FP64, PA_FP32, PA_BF16, PA_BF16_CORR = 0, 1, 2, 3
 PA_ALGO_FORWARD, PA_ALGO_ADJOINT = 0, 1
 PA_ACT_SOFTPLUS = 0
+PA_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 PRECISIONS = {"fp64": PA_FP64, "fp32": PA_FP32, "bf16": PA_BF16, "bf16_corr": PA_BF16_CORR}
 ALGORITHMS = {"forward": PA_ALGO_FORWARD, "adjoint": PA_ALGO_ADJOINT}
@@ -63,6 +64,8 @@ SIGNATURES = {
     "pa_invariants": (C.c_int, [PDESC, I64, P, P, P, P, P]),
     "pa_material_workspace_bytes": (SZ, [PDESC, I64]),
     "pa_energy_stress_tangent": (C.c_int, [PDESC, P, C.c_int, I64, P, P, P, P, P, P, SZ, P]),
+    "pa_energy_stress_tangent_noalloc": (C.c_int, [PDESC, P, C.c_int, I64, P, P, P, P, P, P]),
+    "pa_noalloc_max_points": (I64, [PDESC]),
     "pa_mesh_geometry": (C.c_int, [I32, I64, I64, P, P, P, P, P, P]),
     "pa_element_workspace_bytes": (SZ, [PDESC, PMESH]),
     "pa_element_residual_stiffness": (C.c_int, [PDESC, P, C.c_int, PMESH, P, P, P, P, P, SZ, P]),

@@ -15,7 +15,7 @@ from . import _lib as L
 
 __all__ = ["Model", "FEMesh", "invariants", "energy_stress_tangent", "element_residual_stiffness",
            "assemble_csr", "tangent_build", "param_backward", "num_params", "num_inputs", "PaStress",
-           "stress"]
+           "stress", "energy_stress_tangent_noalloc", "noalloc_max_points"]
 
 
 def _p(t):
@@ -208,6 +208,40 @@ def energy_stress_tangent(model: Model, F, prec="fp64", psi=True, P=True, A=True
         C.byref(model.desc), _p(prep), _prec(prec), n, _p(Fs), _p(out.get("psi")), _p(out.get("P")),
         _p(out.get("A")), _p(n_bad), _p(workspace), workspace.numel(), _stream()), "pa_energy_stress_tangent")
     return out
+
+
+def energy_stress_tangent_noalloc(model: Model, F, prec="fp64", psi=True, P=True, A=True, soa=False,
+                                  n_bad=None, out=None):
+    """``energy_stress_tangent`` through ``pa_energy_stress_tangent_noalloc``:
+    the library takes no workspace from the caller and allocates nothing (its
+    own device scratch array serves); at most ``noalloc_max_points(model)``
+    points per call.  The outputs are the caller's (allocated here when
+    ``out`` is None)."""
+    Fs = F if soa else _soa9(F)
+    n = Fs.shape[1]
+    dev = Fs.device
+    _need(Fs, "F", 9 * n, device=model.device)
+    if out is None:
+        out = {}
+        if psi:
+            out["psi"] = torch.empty(n, dtype=torch.float64, device=dev)
+        if P:
+            out["P"] = torch.empty((9, n), dtype=torch.float64, device=dev)
+        if A:
+            out["A"] = torch.empty((81, n), dtype=torch.float64, device=dev)
+    _need(out.get("psi"), "psi", n, device=model.device)
+    _need(out.get("P"), "P", 9 * n, device=model.device)
+    _need(out.get("A"), "A", 81 * n, device=model.device)
+    _need(n_bad, "n_bad", 1, torch.int32, device=model.device)
+    L.check(model.lib.pa_energy_stress_tangent_noalloc(
+        C.byref(model.desc), _p(model.prepared), _prec(prec), n, _p(Fs), _p(out.get("psi")), _p(out.get("P")),
+        _p(out.get("A")), _p(n_bad), _stream()), "pa_energy_stress_tangent_noalloc")
+    return out
+
+
+def noalloc_max_points(model: Model) -> int:
+    """Largest batch ``energy_stress_tangent_noalloc`` accepts for this model."""
+    return int(model.lib.pa_noalloc_max_points(C.byref(model.desc)))
 
 
 def energy_stress_tangent_voigt(model: Model, F, prec="fp64", psi=True, tau=True, cc=True, soa=False,

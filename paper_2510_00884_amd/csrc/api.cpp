@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -299,6 +300,73 @@ int pa_energy_stress_tangent_voigt(const pa_model_desc* d, const void* prepared,
   if (!workspace || (int64_t)ws_bytes < material_ws(d, n))
     return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)material_ws(d, n));
   return run_material(d, prepared, prec, n, F, psi, tau, cc, n_bad, (unsigned char*)workspace, S(stream), true);
+}
+
+}  // extern "C"
+
+// ---- the allocation-free material call: its workspace is this file-scope
+// device array (one copy per GPU, held until the process ends).  In host
+// code `scratch` names a host-side stand-in, so kernels and copies use the
+// device address that hipGetSymbolAddress returns for the current device.
+namespace {
+static __device__ __align__(256) unsigned char scratch[PA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device with that device current.
+int scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(PA_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PA_ERR_ARG, "device %d outside 0..%d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(PA_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return PA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pa_energy_stress_tangent_noalloc(const pa_model_desc* d, const void* prepared, int prec, int64_t n,
+                                     const double* F, double* psi, double* P, double* A, int32_t* n_bad,
+                                     void* stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if ((rc = check_prec(prec))) return rc;
+  if (n < 0) return fail(PA_ERR_ARG, "n_qp < 0");
+  if (n == 0) return PA_OK;
+  if (!prepared || !F) return fail(PA_ERR_ARG, "prepared and F must be non-NULL");
+  const int64_t need = material_ws(d, n);
+  if (need > (int64_t)PA_NOALLOC_SCRATCH_BYTES)
+    return fail(PA_ERR_WORKSPACE,
+                "pa_energy_stress_tangent_noalloc: %lld points need %lld bytes of scratch, the library holds %lld "
+                "(at most %lld points for this model)",
+                (long long)n, (long long)need, (long long)PA_NOALLOC_SCRATCH_BYTES,
+                (long long)pa_noalloc_max_points(d));
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  return run_material(d, prepared, prec, n, F, psi, P, A, n_bad, (unsigned char*)ws, S(stream));
+}
+
+int64_t pa_noalloc_max_points(const pa_model_desc* d) {
+  if (!d || d->n_sv < 0 || d->n_sv > 2) return 0;
+  // material_ws rounds each of its two arrays up to 256 bytes
+  const int p = p_of(d);
+  const int64_t per_point = 8 * (int64_t)(p + 1 + p + p * (p + 1) / 2);
+  int64_t n = ((int64_t)PA_NOALLOC_SCRATCH_BYTES - 512) / per_point;
+  while (n > 0 && material_ws(d, n) > (int64_t)PA_NOALLOC_SCRATCH_BYTES) --n;
+  while (material_ws(d, n + 1) <= (int64_t)PA_NOALLOC_SCRATCH_BYTES) ++n;
+  return n;
 }
 
 int pa_mesh_geometry(int32_t nen, int64_t n_el, int64_t n_nodes, const double* X, const int32_t* conn,

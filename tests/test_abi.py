@@ -200,3 +200,25 @@ def test_binding_argument_checks_on_host():
         api._need(torch.zeros(9, dtype=torch.float32), "F", 9)
     with pytest.raises(ValueError, match="int32"):
         api._need(torch.zeros(9, dtype=torch.int64), "dof_group", 9, torch.int32)
+
+
+def test_noalloc_limit_checked_before_launch(lib):
+    """The allocation-free material call states its batch limit and refuses a
+    larger batch on the host (PA_ERR_WORKSPACE, nothing launched)."""
+    for n_sv, p in ((0, 3), (1, 5), (2, 9)):
+        d = _desc(n_sv=n_sv)
+        nmax = lib.pa_noalloc_max_points(C.byref(d))
+        need = lib.pa_material_workspace_bytes(C.byref(d), nmax)
+        assert 0 < need <= L.PA_NOALLOC_SCRATCH_BYTES
+        assert lib.pa_material_workspace_bytes(C.byref(d), nmax + 1) > L.PA_NOALLOC_SCRATCH_BYTES
+    d = _desc(n_sv=2)
+    assert lib.pa_noalloc_max_points(C.byref(d)) == 131072
+    rc = lib.pa_energy_stress_tangent_noalloc(C.byref(d), C.c_void_p(8), 0, 131073, C.c_void_p(8), None, None, None,
+                                             None, None)
+    assert rc == L.PA_ERR_WORKSPACE
+    assert b"131072" in lib.pa_last_error()
+    rc = lib.pa_energy_stress_tangent_noalloc(C.byref(d), C.c_void_p(8), 0, -1, C.c_void_p(8), None, None, None,
+                                             None, None)
+    assert rc == L.PA_ERR_ARG
+    assert lib.pa_energy_stress_tangent_noalloc(C.byref(d), C.c_void_p(8), 0, 0, None, None, None, None, None,
+                                               None) == L.PA_OK
