@@ -26,7 +26,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "bf16_corr": 2.5e15}
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "bf16_corr": 2.5e15, "bf16_jac": 2.5e15}
 HBM_PEAK = 8.0e12
 
 
@@ -181,8 +181,8 @@ def other_workload(args):
         F = torch.tensor(synth.sample_F(n, seed=0), device="cuda")
         res = {}
         ref = None
-        for prec, algo in [("fp64", "adjoint"), ("fp32", "adjoint"), ("bf16_corr", "adjoint"), ("bf16", "forward"),
-                           ("bf16_corr", "forward"), ("fp64", "forward")]:
+        for prec, algo in [("fp64", "adjoint"), ("fp32", "adjoint"), ("bf16", "adjoint"), ("bf16_corr", "adjoint"),
+                           ("bf16_jac", "adjoint"), ("bf16", "forward"), ("bf16_corr", "forward"), ("fp64", "forward")]:
             gm = api.Model(theta, n_sv, h, Lh, A=Av, normalize=True, algorithm=algo)
             bufs = {}
             def call():
@@ -303,10 +303,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=64, help="cubes per side of the hex8 mesh")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16", "bf16_corr"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16", "bf16_corr", "bf16_jac"])
     ap.add_argument("--algo", default="adjoint", choices=["forward", "adjoint"],
                     help="network Hessian formation (BF16 variants always use forward)")
-    ap.add_argument("--variants", default="fp32,bf16,bf16_corr",
+    ap.add_argument("--variants", default="fp32,bf16,bf16_corr,bf16_jac",
                     help="other precisions timed after the headline run ('' for none)")
     ap.add_argument("--workload", default="hex8_64",
                     choices=["hex8_64", "points_2pow22", "calib_2pow20", "tet10_56", "model_sweep"],
@@ -442,7 +442,7 @@ def main():
     variants = {}
     for vp in [x for x in args.variants.split(",") if x and x not in ("none", args.prec)]:
         # the adjoint form has FP64, FP32 and BF16-with-FP32-correction kernels
-        model.algorithm = args.algo if vp in ("fp64", "fp32", "bf16_corr") else "forward"
+        model.algorithm = args.algo
         vms, vk = run(vp, max(args.steps // 2, 2), 1, True)
         err_r = (bufs["r"] - r_ref).norm().item() / r_ref.norm().item()
         err_K = (bufs["vals"] - v_ref).norm().item() / v_ref.norm().item()
@@ -469,7 +469,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "bf16_corr": "bf16+f32"}[args.prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "bf16_corr": "bf16+f32", "bf16_jac": "f32+bf16"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"hex8 {n}^3 unit cube, orthotropic e1/e2 (9 inputs), MICNN 2x32 softplus, "
                                "one Newton tangent build: residual + tangent + CSR assembly",

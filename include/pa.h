@@ -48,14 +48,22 @@ typedef enum {
   PA_ERR_WORKSPACE = -4    /* workspace NULL or smaller than required          */
 } pa_status;
 
-/* Arithmetic of the inner-network contractions (matrix cores). */
+/* Arithmetic of the inner-network contractions (matrix cores).  Every mode
+ * takes and returns FP64 arrays; kinematics, chain rule and elements are FP64. */
 typedef enum {
   PA_FP64 = 0,      /* FP64 MFMA                                              */
   PA_FP32 = 1,      /* FP32 MFMA, FP32 activations                            */
-  PA_BF16 = 2,      /* BF16 MFMA inputs, FP32 accumulation and activations    */
-  PA_BF16_CORR = 3  /* value and first-derivative columns recomputed in FP32
-                       MFMA (the correction pass), second-derivative columns
-                       in BF16                                               */
+  PA_BF16 = 2,      /* every contraction (value, gradient and Hessian) on
+                       BF16 MFMA inputs with FP32 accumulation and FP32
+                       activations                                           */
+  PA_BF16_CORR = 3, /* the PA_BF16 pass, then a correction pass that
+                       recomputes the value and first-derivative columns with
+                       FP32 MFMA and overwrites them; the second-derivative
+                       columns keep the BF16 result (both algorithms)         */
+  PA_BF16_JAC = 4   /* one mixed pass, PA_ALGO_ADJOINT only: value, reverse
+                       sweep, gradient and layer-1 Hessian term in FP32, the
+                       Jacobians of layers >= 2 (the bulk of the Hessian work)
+                       on the BF16 matrix cores                              */
 } pa_precision;
 
 /* How the network's input Hessian is formed.  Both give the same numbers up
@@ -65,11 +73,9 @@ typedef enum {
                           gradient and Hessian columns carried layer by layer */
   PA_ALGO_ADJOINT = 1  /* value forward, value adjoint backward, then the
                           Jacobian forward accumulating the Hessian as
-                          sum_k J_k^T diag(lambda_k F''(y_k)) J_k; FP64,
-                          FP32 and PA_BF16_CORR (value, gradient, reverse
-                          sweep and layer-1 term in FP32, the Jacobians of
-                          layers >= 2 on the BF16 matrix cores with FP32
-                          accumulation); PA_BF16: PA_ERR_UNSUPPORTED         */
+                          sum_k J_k^T diag(lambda_k F''(y_k)) J_k; every
+                          precision (PA_BF16 and PA_BF16_CORR: two or three
+                          hidden layers)                                      */
 } pa_algorithm;
 
 typedef enum { PA_ACT_SOFTPLUS = 0 } pa_activation;
@@ -107,8 +113,8 @@ typedef struct {
   int32_t n_sv;        /* number of structural vectors: 0, 1 or 2           */
   double  A[2][3];     /* reference structural vectors A^1, A^2              */
   int32_t n_hidden;    /* L: hidden layers, 2, 3 or 4 (4: PA_ALGO_ADJOINT
-                        * and the parameter adjoint only; forward mode and
-                        * the BF16 precisions return PA_ERR_UNSUPPORTED)    */
+                        * with PA_FP64, PA_FP32 or PA_BF16_JAC, and the
+                        * parameter adjoint; otherwise PA_ERR_UNSUPPORTED)  */
   int32_t width;       /* h: neurons per hidden layer: 1..16, 32 or 64.
                         * Widths below 16 run zero-padded to 16 neurons
                         * (same outputs, the cost of width 16)              */

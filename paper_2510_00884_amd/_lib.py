@@ -12,12 +12,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpa.so")
 
 PA_OK, PA_ERR_ARG, PA_ERR_UNSUPPORTED, PA_ERR_HIP, PA_ERR_WORKSPACE = 0, -1, -2, -3, -4
-PA_FP64, PA_FP32, PA_BF16, PA_BF16_CORR = 0, 1, 2, 3
+PA_FP64, PA_FP32, PA_BF16, PA_BF16_CORR, PA_BF16_JAC = 0, 1, 2, 3, 4
 PA_ALGO_FORWARD, PA_ALGO_ADJOINT = 0, 1
 PA_ACT_SOFTPLUS = 0
 PA_NOALLOC_SCRATCH_BYTES = 64 << 20
 
-PRECISIONS = {"fp64": PA_FP64, "fp32": PA_FP32, "bf16": PA_BF16, "bf16_corr": PA_BF16_CORR}
+PRECISIONS = {"fp64": PA_FP64, "fp32": PA_FP32, "bf16": PA_BF16, "bf16_corr": PA_BF16_CORR, "bf16_jac": PA_BF16_JAC}
 ALGORITHMS = {"forward": PA_ALGO_FORWARD, "adjoint": PA_ALGO_ADJOINT}
 PA_MODEL_MICNN, PA_MODEL_CANN, PA_MODEL_GENT_THOMAS = 0, 1, 2
 MODEL_KINDS = {"micnn": PA_MODEL_MICNN, "cann": PA_MODEL_CANN, "gent_thomas": PA_MODEL_GENT_THOMAS}

@@ -95,7 +95,8 @@ class Model:
         """kind: "micnn" (eq. icnn), "cann" (App. B.1) or "gent_thomas" (eq. gt);
         width (1..16, 32 or 64) and n_hidden (2..4) apply to the MICNN only.
         algorithm: "forward" (Alg. 4; 2-3 hidden layers, every precision) or
-        "adjoint" (adjoint-form Hessian; FP64, FP32 and "bf16_corr")."""
+        "adjoint" (adjoint-form Hessian; every precision: "fp64", "fp32", "bf16",
+        "bf16_corr" and the mixed one-pass "bf16_jac")."""
         self.lib = L.load()
         self.desc = _desc(n_sv, width, n_hidden, A, normalize, has_bias, algorithm, kind)
         self.n_sv, self.width, self.n_hidden = int(n_sv), int(width), int(n_hidden)

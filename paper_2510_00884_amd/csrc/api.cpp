@@ -138,7 +138,7 @@ int64_t material_ws(const pa_model_desc* d, int64_t n) {
 }
 
 int check_prec(int prec) {
-  if (prec < PA_FP64 || prec > PA_BF16_CORR) return fail(PA_ERR_ARG, "unknown precision %d", prec);
+  if (prec < PA_FP64 || prec > PA_BF16_JAC) return fail(PA_ERR_ARG, "unknown precision %d", prec);
   return PA_OK;
 }
 

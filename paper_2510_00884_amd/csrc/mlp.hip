@@ -70,6 +70,12 @@ PrepLayout prep_layout(int H, int L, int P) {
   }
   l.x_ATp = take(8 * (int64_t)L * l.MB * l.SH * 64);
   l.y_ATp = take(4 * (int64_t)L * l.MB * l.SH * 64);
+  {
+    const int npb = (P * (P + 1) / 2 + 15) / 16;
+    l.w_AT = take(16 * (int64_t)L * l.MB * l.SHB * 64);
+    l.w_GT = take(16 * (int64_t)L * l.SHB * 64);
+    l.w_G1 = take(16 * (int64_t)npb * l.SHB * 64);
+  }
   l.k0 = take(8 * (int64_t)P * 16);
   l.nout = take(8 * (int64_t)l.NOUT * 16);
   l.total = o;
@@ -276,6 +282,53 @@ __global__ void k_prep_frags(const double* __restrict__ th, ThetaLayout t, PrepL
   }
 }
 
+// K position 8g + e of BF16 product step t -> neuron (the accumulator-row
+// order of the previous product's result).
+__device__ inline int kperm_row(int t, int g, int e) { return e < 4 ? 32 * t + 4 * g + e : 32 * t + 16 + 4 * g + e - 4; }
+
+// Fragments of the all-BF16 adjoint form (layout in PrepLayout::w_*).
+__global__ void k_prep_bf16(const double* __restrict__ th, ThetaLayout t, PrepLayout l,
+                            unsigned char* __restrict__ prep) {
+  const int H = l.H, P = l.P, L = l.L, MB = l.MB, SHB = l.SHB;
+  const int P2 = P * (P + 1) / 2, NPB = (P2 + 15) / 16;
+  __bf16* wAT = (__bf16*)(prep + l.w_AT);
+  __bf16* wGT = (__bf16*)(prep + l.w_GT);
+  __bf16* wG1 = (__bf16*)(prep + l.w_G1);
+  const int64_t nAT = (int64_t)L * MB * SHB * 512, nGT = (int64_t)L * SHB * 512, nG1 = (int64_t)NPB * SHB * 512;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nAT + nGT + nG1;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j = idx;
+    const int e = (int)(j % 8), lane = (int)((j / 8) % 64), i = lane & 15, g = lane >> 4;
+    if (j < nAT) {  // [k-1][mb][tt][lane][e]: A_k[r][16 mb + i]
+      const int tt = (int)((j / 512) % SHB), mb = (int)((j / (512 * SHB)) % MB), k = (int)(j / (512 * SHB * MB)) + 1;
+      const int r = kperm_row(tt, g, e);
+      wAT[j] = (__bf16)(float)((k >= 2 && r < H) ? th_w(th, t, k, r, 16 * mb + i) : 0.0);
+      continue;
+    }
+    j -= nAT;
+    if (j < nGT) {  // [k-1][tt][lane][e]: W1[r][i] or B_k[r][i]
+      const int tt = (int)((j / 512) % SHB), k = (int)(j / (512 * SHB)) + 1;
+      const int r = kperm_row(tt, g, e);
+      double v = 0.0;
+      if (i < P && r < H) v = (k == 1) ? th_w(th, t, 1, r, i) : th_skip(th, t, k, r, i);
+      wGT[j] = (__bf16)(float)v;
+      continue;
+    }
+    j -= nGT;
+    {  // [pb][tt][lane][e]: W1[r][m] W1[r][nn], pair 16 pb + i = (m, nn), m <= nn, row-major packed
+      const int tt = (int)((j / 512) % SHB), pb = (int)(j / (512 * SHB));
+      const int r = kperm_row(tt, g, e), pair = 16 * pb + i;
+      double v = 0.0;
+      if (pair < P2 && r < H) {
+        int h = pair, m = 0;
+        while (h >= P - m) { h -= P - m; ++m; }
+        v = th_w(th, t, 1, r, m) * th_w(th, t, 1, r, m + h);
+      }
+      wG1[j] = (__bf16)(float)v;
+    }
+  }
+}
+
 // Normalisation: N0 = N(0), kappa_q = dN/dK_{4,q}(0) + 2 dN/dK_{5,q}(0);
 // b_{4,q} -= kappa_q so that P(I) = 0; Psi = N - N0.
 __global__ void k_prep_fold(PrepLayout l, unsigned char* __restrict__ prep, int normalize, int npair) {
@@ -344,6 +397,7 @@ int launch_prepare(const PrepLayout& lay, const ThetaLayout& tl, const double* t
                    unsigned char* prep, int normalize, int npair, hipStream_t s) {
   k_prep_tables<<<64, 256, 0, s>>>(theta, tl, lay, prep);
   k_prep_frags<<<256, 256, 0, s>>>(theta, tl, lay, prep);
+  k_prep_bf16<<<64, 256, 0, s>>>(theta, tl, lay, prep);
   if (normalize) {
     const int algo = mlp_fwd_supported(lay.H, lay.L, lay.P) ? 0 : 1;
     int rc = launch_mlp(lay, PREC_F64, algo, prep, 1, (const double*)(prep + lay.k0),

@@ -5,6 +5,7 @@
 #include <type_traits>
 #include <utility>
 
+#include "mlp_bf16.h"
 #include "mma_util.h"
 #include "pa_internal.h"
 
@@ -28,15 +29,6 @@ namespace pa {
 //      formed, so the vector work overlaps the next column's matrix
 //      products, and reduced four pairs at a time into the output tile.
 // Points on the N dimension, neurons split across waves as in k_mlp_fwd.
-// Pair t of the column-major upper triangle (m = column, n <= m).
-__host__ __device__ constexpr int colmaj_m(int t) {
-  int m = 0;
-  while (t > m) { t -= m + 1; ++m; }
-  return m;
-}
-__host__ __device__ constexpr int colmaj_n(int t) { return t - colmaj_m(t) * (colmaj_m(t) + 1) / 2; }
-// Packed row-major index of pair (n, m), n <= m.
-__host__ __device__ constexpr int packed_index(int n, int m, int P) { return n * P - n * (n - 1) / 2 + (m - n); }
 
 template <int H, int L, int P, int PR, bool HESS, bool PERSIST = !HESS>
 __global__ void __launch_bounds__(64 * (H / 16))
@@ -84,10 +76,10 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 #pragma unroll
     for (int s = 0; s < S1; ++s) BV[k - 2][s] = fB[(((k - 1) * MB + w) * S1 + s) * 64 + lane];
   }
-  // PREC_BF16C: the Jacobian pass of layers >= 2 runs on the BF16 matrix
+  // PREC_BF16J: the Jacobian pass of layers >= 2 runs on the BF16 matrix
   // cores (these fragments, K permuted to the FP32 accumulator layout);
   // value, reverse sweep, gradient and the layer-1 Gram stay FP32
-  constexpr bool JB = PR == PREC_BF16C;
+  constexpr bool JB = PR == PREC_BF16J;
   constexpr int SHB = (H + 31) / 32;
   bf16x8 AZ[JB ? L - 1 : 1][JB ? SHB : 1];
   if constexpr (JB && HESS) {
@@ -550,12 +542,12 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     // ---- layer-2 Jacobian, one row block at a time, Gram pairs as columns form
 #pragma unroll 1
     for (int ob = 0; ob < MB; ++ob) {
-      // PREC_BF16C: the layer-2 Jacobian contracts over the neurons on the
+      // PREC_BF16J: the layer-2 Jacobian contracts over the neurons on the
       // BF16 matrix cores (16x16x32, FP32 accumulation; the K dimension of
       // the prepared BF16 fragments is permuted to the FP32 accumulator
       // layout, so the column sources pack without shuffles); everything
       // else in this kernel is FP32
-      constexpr bool JB = PR == PREC_BF16C;
+      constexpr bool JB = PR == PREC_BF16J;
       constexpr int SHB = (H + 31) / 32;
       frag_t AV[JB ? 1 : SH];
       bf16x8 AZ[JB ? SHB : 1];
@@ -734,9 +726,39 @@ static void launch_adj2_one(const PrepLayout& lay, const unsigned char* prep, in
   k_mlp_adj2<H, P, PR, HESS><<<grid, 256, 0, s>>>(prep, lay, n, K, out);
 }
 
+template <int H, int L, int P, bool HESS>
+static void launch_bf16_one(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
+                            double* out, hipStream_t s) {
+  const int64_t nblk = ((n + 15) / 16 + 3) / 4;
+  k_mlp_bf16<H, L, P, HESS><<<persistent_grid(k_mlp_bf16<H, L, P, HESS>, 256, nblk), 256, 0, s>>>(prep, lay, n, K,
+                                                                                                   out);
+}
+
+// FP32 value and gradient only (no Hessian): the correction pass of PREC_BF16C.
+template <int H, int L, int P>
+static void launch_fp32_grad(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
+                             double* out, hipStream_t s) {
+  if constexpr (L == 2 && H <= 32)
+    launch_adj2_one<H, P, PREC_F32, false>(lay, prep, n, K, out, s);
+  else
+    launch_adj_one<H, L, P, PREC_F32, false>(lay, prep, n, K, out, s);
+}
+
 template <int H, int L, int P>
 static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char* prep, int64_t n,
                             const double* K, double* out, int hess, hipStream_t s) {
+  // all-BF16 (two and three hidden layers), optionally followed by the FP32
+  // pass that rewrites the value and gradient columns
+  if (prec == PREC_BF16 || prec == PREC_BF16C) {
+    if constexpr (L <= 3) {
+      if (hess) launch_bf16_one<H, L, P, true>(lay, prep, n, K, out, s);
+      else launch_bf16_one<H, L, P, false>(lay, prep, n, K, out, s);
+      if (prec == PREC_BF16C) launch_fp32_grad<H, L, P>(lay, prep, n, K, out, s);
+      return 0;
+    } else {
+      return -2;
+    }
+  }
   if constexpr (L == 2 && H <= 32) {
     switch (prec) {
       case PREC_F64:
@@ -747,8 +769,8 @@ static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char
         if (hess) launch_adj2_one<H, P, PREC_F32, true>(lay, prep, n, K, out, s);
         else launch_adj2_one<H, P, PREC_F32, false>(lay, prep, n, K, out, s);
         return 0;
-      case PREC_BF16C:  // FP32 value and gradient, layer-2 Jacobian in BF16
-        if (hess) launch_adj2_one<H, P, PREC_BF16C, true>(lay, prep, n, K, out, s);
+      case PREC_BF16J:  // FP32 value and gradient, layer-2 Jacobian in BF16
+        if (hess) launch_adj2_one<H, P, PREC_BF16J, true>(lay, prep, n, K, out, s);
         else launch_adj2_one<H, P, PREC_F32, false>(lay, prep, n, K, out, s);
         return 0;
       default: return -2;
@@ -763,8 +785,8 @@ static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char
       if (hess) launch_adj_one<H, L, P, PREC_F32, true>(lay, prep, n, K, out, s);
       else launch_adj_one<H, L, P, PREC_F32, false>(lay, prep, n, K, out, s);
       break;
-    case PREC_BF16C:  // FP32 value and gradient, Jacobian pass in BF16
-      if (hess) launch_adj_one<H, L, P, PREC_BF16C, true>(lay, prep, n, K, out, s);
+    case PREC_BF16J:  // FP32 value and gradient, Jacobian pass in BF16
+      if (hess) launch_adj_one<H, L, P, PREC_BF16J, true>(lay, prep, n, K, out, s);
       else launch_adj_one<H, L, P, PREC_F32, false>(lay, prep, n, K, out, s);
       break;
     default: return -2;

@@ -332,7 +332,7 @@ static int launch_mlp_t(const PrepLayout& lay, int prec, const unsigned char* pr
     case PREC_F32: k_mlp_fwd<H, L, P, PREC_F32><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
     case PREC_BF16: k_mlp_fwd<H, L, P, PREC_BF16><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
     case PREC_BF16C: k_mlp_fwd<H, L, P, PREC_BF16C><<<grid, block, 0, s>>>(prep, lay, n, K, out, hess); break;
-    default: return -1;
+    default: return -2;  // PREC_BF16J: adjoint form only
   }
   return 0;
 }

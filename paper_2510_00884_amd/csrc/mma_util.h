@@ -94,14 +94,27 @@ __device__ constexpr int hess_n(int h, int P) {
   return 0;
 }
 
+// Pair t of the column-major upper triangle (m = column, n <= m).
+__host__ __device__ constexpr int colmaj_m(int t) {
+  int m = 0;
+  while (t > m) { t -= m + 1; ++m; }
+  return m;
+}
+__host__ __device__ constexpr int colmaj_n(int t) { return t - colmaj_m(t) * (colmaj_m(t) + 1) / 2; }
+// Packed row-major index of pair (n, m), n <= m.
+__host__ __device__ constexpr int packed_index(int n, int m, int P) { return n * P - n * (n - 1) / 2 + (m - n); }
+
 template <class E> __device__ inline typename E::acc zero_acc() { return typename E::acc{0, 0, 0, 0}; }
 
 // Exchanges between lane halves on gfx950 (checked on the device):
 // swap32(a, b) leaves a = [a lanes 0-31, b lanes 0-31] and
 // b = [a lanes 32-63, b lanes 32-63]; swap16(a, b) does the same with the
 // 16-lane rows, a = [a.r0, b.r0, a.r2, b.r2], b = [a.r1, b.r1, a.r3, b.r3].
-// A double moves as its two dwords.
+// A double moves as its two dwords.  The operands are pinned to distinct
+// registers first: the compiler may otherwise treat a swap of two equal
+// values as a no-op and reuse one result for both.
 __device__ inline void swap32(double& a, double& b) {
+  asm volatile("" : "+v"(a), "+v"(b));
   const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
   const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
   const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
@@ -110,6 +123,7 @@ __device__ inline void swap32(double& a, double& b) {
   b = __builtin_bit_cast(double, (unsigned long long)lo[1] | ((unsigned long long)hi[1] << 32));
 }
 __device__ inline void swap16(double& a, double& b) {
+  asm volatile("" : "+v"(a), "+v"(b));
   const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
   const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
   const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);

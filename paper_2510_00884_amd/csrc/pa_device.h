@@ -11,7 +11,11 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16C = 3 };
+// Network-contraction precisions (the values of pa_precision): FP64, FP32,
+// all-BF16, all-BF16 followed by an FP32 pass over the value and gradient,
+// and the one-pass mixed form (FP32 value, gradient and reverse sweep, BF16
+// Jacobians of layers >= 2).
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16C = 3, PREC_BF16J = 4 };
 
 // ---------------------------------------------------------------------------
 // Matrix-core engines.  One instruction multiplies a 16 x KS block of A by a

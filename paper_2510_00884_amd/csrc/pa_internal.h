@@ -31,6 +31,12 @@ struct PrepLayout {
   int64_t x_AT, y_AT;   // transposed hidden weights for reverse products [L][MB][SH][64]
   int64_t x_G1, y_G1;   // layer-1 Gram table W1_rm W1_rn as MFMA A fragments [NPB][MB][4][64]
   int64_t x_ATp, y_ATp; // transposed hidden weights, K steps in accumulator-row order [L][MB][SH][64]
+  // BF16 fragments of the all-BF16 adjoint form, K in the permuted neuron
+  // order of the 16x16x32 products (position 8g + e of step t: neuron
+  // 32t + 4g + e, e < 4; 32t + 16 + 4g + e - 4, e >= 4), [..][64][8]:
+  int64_t w_AT;  // [L][MB][SHB]: lane (i, g) of row block mb holds A_k[neuron][16 mb + i]
+  int64_t w_GT;  // [L][SHB]: row i = input: W1[neuron][i] (k = 1), B_k[neuron][i]
+  int64_t w_G1;  // [NPB][SHB]: row i = packed pair 16 pb + i: W1[neuron][m] W1[neuron][n]
   int64_t k0, nout;
   int64_t total;
 };
