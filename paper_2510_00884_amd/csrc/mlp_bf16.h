@@ -60,6 +60,20 @@ __device__ inline void half_pairs(const bf16x8& x, int h, bf16x2& a, bf16x2& b) 
 
 __device__ inline float bf16_to_f32(__bf16 x) { return (float)x; }
 
+// Softplus, F' and F'' from the hardware base-2 exponential and logarithm and
+// the reciprocal estimate (about one ulp each): e = e^{-|y|},
+// F = max(y, 0) + ln(1 + e), F' = 1/(1 + e) (y >= 0) or e/(1 + e), F'' =
+// e/(1 + e)^2.  ln(1 + e) is formed from the rounded 1 + e, an absolute
+// error of a few 1e-8, far below the BF16 rounding of every product here.
+__device__ inline void softplus3_fast(float y, float& f, float& f1, float& f2) {
+  const float e = __builtin_amdgcn_exp2f(-fabsf(y) * 1.44269504088896341f);
+  const float d = 1.0f + e;
+  const float r = __builtin_amdgcn_rcpf(d);
+  f = fmaxf(y, 0.0f) + __builtin_amdgcn_logf(d) * 0.693147180559945309f;
+  f1 = (y >= 0.0f) ? r : e * r;
+  f2 = e * r * r;
+}
+
 // Cross-lane sums in FP32 through lane shuffles.  (The in-place lane-swap
 // instructions exchange two registers; the compiler folds such swaps
 // wrongly when an operand is a known constant, e.g. the zero partial of a
@@ -78,8 +92,14 @@ __device__ inline float reduce4f(float p0, float p1, float p2, float p3, int g) 
   return (even ? a : b) + __shfl_xor(even ? b : a, 16);
 }
 
+// Waves per SIMD the register budget is sized for: two (256 registers) for
+// two hidden layers; one (512) for three, whose Hessian pass keeps the
+// packed layer-3 sources of every input column live.
+template <int L, bool HESS>
+constexpr int bf16_waves() { return (L == 3 && HESS) ? 1 : 2; }
+
 template <int H, int L, int P, bool HESS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bf16_waves<L, HESS>())))
 k_mlp_bf16(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n, const double* __restrict__ Kin,
            double* __restrict__ out) {
   static_assert(L == 2 || L == 3, "two or three hidden layers");
@@ -191,7 +211,7 @@ k_mlp_bf16(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n, co
         const f4 acc = mfma(sW1[mb * 64 + lane], kb, (f4){0.f, 0.f, 0.f, 0.f});
         const f4 c = row4(sc, mb);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) softplus3(acc[v] + c[v], z[mb][v], s1[mb][v], t1[mb][v]);
+        for (int v = 0; v < 4; ++v) softplus3_fast(acc[v] + c[v], z[mb][v], s1[mb][v], t1[mb][v]);
       }
       pack_rows<MB>(z, zsrc);
     }
@@ -206,7 +226,7 @@ k_mlp_bf16(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n, co
         for (int t = 0; t < SHB; ++t) acc = mfma(sA[(((k - 2) * MB + ob) * SHB + t) * 64 + lane], zsrc[t], acc);
         const f4 c = row4(sc + (k - 1) * H, ob);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) softplus3(acc[v] + c[v], z[ob][v], sK[k - 2][ob][v], tK[k - 2][ob][v]);
+        for (int v = 0; v < 4; ++v) softplus3_fast(acc[v] + c[v], z[ob][v], sK[k - 2][ob][v], tK[k - 2][ob][v]);
       }
       if constexpr (k < L) {
         pack_rows<MB>(z, zsrc);
@@ -228,6 +248,7 @@ k_mlp_bf16(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n, co
     // the gradient W1^T mu_1 + sum_k B_k^T mu_k accumulates on the matrix cores
     float gm[L - 1][MB][4];  // gamma of layers 2..L (kept for the Jacobian pass)
     float g1[MB][4];         // gamma_1
+    float lam2[L == 3 ? MB : 1][4];  // lambda_2 (three hidden layers)
     f4 gacc = {0.f, 0.f, 0.f, 0.f};
     {
       float mu[MB][4];
@@ -256,6 +277,7 @@ k_mlp_bf16(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n, co
             if constexpr (k - 1 >= 2) {
               mu[mb][v] = acc[v] * sK[k - 3][mb][v];
               gm[k - 3][mb][v] = acc[v] * tK[k - 3][mb][v];
+              if constexpr (L == 3) lam2[mb][v] = acc[v];
             } else {
               mu[mb][v] = acc[v] * s1[mb][v];
               g1[mb][v] = acc[v] * t1[mb][v];
@@ -289,26 +311,94 @@ k_mlp_bf16(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n, co
       }
     }
 
+    // layer-2 Gram weights gamma_2 / s_2 (three hidden layers)
+    float w2[L == 3 ? MB : 1][4];
+    if constexpr (L == 3) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w2[mb][v] = lam2[mb][v] * (1.0f - sK[0][mb][v]);
+    }
     // ---- Jacobian forward of the later layers
-    // sources of the last layer's Jacobian columns: L = 2, s_1 (.) W1[:, m];
-    // L = 3, s_2 (.) J_2[:, m] (the layer-2 Jacobian is formed whole here)
-    bf16x8 src[P][SHB];
-    static_for<P>([&](auto MI) {
-      constexpr int m = decltype(MI)::value;
-      float u[MB][4];
+    // four packed pairs (16 pb + v + 4 j) per cross-lane reduction, which
+    // leaves pair 16 pb + 4 g + v in lane group g: the layout of hacc
+    auto reduce_pairs = [&](const float (&pp)[P2]) {
+      static_for<NPB * 4>([&](auto GI) {
+        constexpr int pb = decltype(GI)::value / 4, v = decltype(GI)::value % 4;
+        if constexpr (16 * pb + v < P2) {
+          constexpr int h0 = 16 * pb + v;
+          hacc[pb][v] += reduce4f(pp[h0], (h0 + 4 < P2) ? pp[h0 + 4 < P2 ? h0 + 4 : 0] : 0.f,
+                                  (h0 + 8 < P2) ? pp[h0 + 8 < P2 ? h0 + 8 : 0] : 0.f,
+                                  (h0 + 12 < P2) ? pp[h0 + 12 < P2 ? h0 + 12 : 0] : 0.f, g);
+        }
+      });
+    };
+    // per-lane pair partials sum_r x_rn y_rm over this lane's four rows
+    auto add_pairs = [&](float (&pp)[P2], const bf16x2 (&x)[P][2], const bf16x2 (&y)[P][2]) {
+      static_for<P2>([&](auto HI) {
+        constexpr int h = decltype(HI)::value;
+        constexpr int a = hess_m(h, P), b = hess_n(h, P);  // pair (a, b), a <= b
+        pp[h] = dot2(x[a][1], y[b][1], dot2(x[a][0], y[b][0], pp[h]));
+      });
+    };
+    if constexpr (L == 2) {
+      // sources of the layer-2 Jacobian columns, s_1 (.) W1[:, m]; the
+      // columns are formed one row block at a time
+      bf16x8 src[P][SHB];
+      static_for<P>([&](auto MI) {
+        constexpr int m = decltype(MI)::value;
+        float u[MB][4];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const f4 wv = row4(sW1t + m * H, mb);
+        for (int mb = 0; mb < MB; ++mb) {
+          const f4 wv = row4(sW1t + m * H, mb);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) u[mb][v] = s1[mb][v] * wv[v];
-      }
-      if constexpr (L == 2) {
+          for (int v = 0; v < 4; ++v) u[mb][v] = s1[mb][v] * wv[v];
+        }
         pack_rows<MB>(u, src[m]);
-      } else {
+      });
+      float pp[P2];
+#pragma unroll
+      for (int i = 0; i < P2; ++i) pp[i] = 0.f;
+      static_for<MB>([&](auto OB) {
+        constexpr int ob = decltype(OB)::value;
+        const bf16x8* aL = sA + ob * SHB * 64 + lane;
+        bf16x2 jp[P][2], gJ[P][2];  // J_2[ob, m] and gamma_2 J_2[ob, m], packed
+        static_for<P>([&](auto MI) {
+          constexpr int m = decltype(MI)::value;
+          f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int t = 0; t < SHB; ++t) acc = mfma(aL[t * 64], src[m][t], acc);
+          const f4 bv = row4(sBt + m * H, ob);
+          float J[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) J[v] = acc[v] + bv[v];
+          jp[m][0] = pk_bf16(J[0], J[1]);
+          jp[m][1] = pk_bf16(J[2], J[3]);
+          gJ[m][0] = pk_bf16(gm[0][ob][0] * J[0], gm[0][ob][1] * J[1]);
+          gJ[m][1] = pk_bf16(gm[0][ob][2] * J[2], gm[0][ob][3] * J[3]);
+        });
+        add_pairs(pp, gJ, jp);
+      });
+      reduce_pairs(pp);
+    } else {
+      // layer 2 whole: the layer-3 sources src3 = s_2 (.) J_2[:, m] and the
+      // layer-2 Gram operands q2 = (gamma_2 / s_2) (.) J_2[:, m], so that
+      // sum_r gamma_2 J_rn J_rm = sum_r q2_rn src3_rm (gamma_2 / s_2 =
+      // lambda_2 (1 - s_2), no division)
+      bf16x8 src3[P][SHB], q2[P][SHB];
+      static_for<P>([&](auto MI) {
+        constexpr int m = decltype(MI)::value;
+        float u[MB][4];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const f4 wv = row4(sW1t + m * H, mb);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) u[mb][v] = s1[mb][v] * wv[v];
+        }
         asm volatile("" ::: "memory");  // layer-2 fragments are re-read per column, not held
         bf16x8 s2src[SHB];
         pack_rows<MB>(u, s2src);
-        float j2[MB][4];
+        float j2s[MB][4], j2q[MB][4];
 #pragma unroll
         for (int ob = 0; ob < MB; ++ob) {
           f4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -316,101 +406,44 @@ k_mlp_bf16(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n, co
           for (int t = 0; t < SHB; ++t) acc = mfma(sA[(ob * SHB + t) * 64 + lane], s2src[t], acc);
           const f4 bv = row4(sBt + m * H, ob);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) j2[ob][v] = sK[0][ob][v] * (acc[v] + bv[v]);
-        }
-        pack_rows<MB>(j2, src[m]);
-      }
-    });
-    // Gram weights of layer 2 on the packed sources s_2 J_2: gamma_2 / s_2^2
-    // (points whose s_2 underflows contribute nothing at FP32 precision)
-    float w2[L == 3 ? MB : 1][4];
-    if constexpr (L == 3) {
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float sv = sK[0][mb][v];
-          w2[mb][v] = (sv > 1e-15f) ? gm[0][mb][v] / (sv * sv) : 0.f;
-        }
-    }
-    // four packed pairs (16 pb + v + 4 j) per cross-lane reduction, which
-    // leaves pair 16 pb + 4 g + v in lane group g: the layout of hacc
-    auto add_pairs = [&](const bf16x2 (&x)[P][2], const bf16x2 (&y)[P][2]) {
-      static_for<NPB * 4>([&](auto GI) {
-        constexpr int pb = decltype(GI)::value / 4, v = decltype(GI)::value % 4;
-        float part[4];
-        static_for<4>([&](auto JI) {
-          constexpr int h = 16 * pb + v + 4 * decltype(JI)::value;
-          float acc = 0.f;
-          if constexpr (h < P2) {
-            constexpr int a = hess_m(h, P), b = hess_n(h, P);  // pair (a, b), a <= b
-            acc = dot2(x[a][0], y[b][0], acc);
-            acc = dot2(x[a][1], y[b][1], acc);
+          for (int v = 0; v < 4; ++v) {
+            const float j = acc[v] + bv[v];
+            j2s[ob][v] = sK[0][ob][v] * j;
+            j2q[ob][v] = w2[ob][v] * j;
           }
-          part[decltype(JI)::value] = acc;
-        });
-        if constexpr (16 * pb + v < P2) hacc[pb][v] += reduce4f(part[0], part[1], part[2], part[3], g);
-      });
-    };
-    if constexpr (L == 3) {
-      // layer-2 Gram from the sources: row block ob of s_2 J_2 is half
-      // (ob % 2) of K step ob / 2
-#pragma unroll 1
-      for (int ob = 0; ob < MB; ++ob) {
-        float wl[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          wl[v] = w2[0][v];
-#pragma unroll
-          for (int b = 1; b < MB; ++b) wl[v] = (ob == b) ? w2[b][v] : wl[v];
         }
-        bf16x2 vp[P][2], u2[P][2];
+        pack_rows<MB>(j2s, src3[m]);
+        pack_rows<MB>(j2q, q2[m]);
+      });
+      float pp[P2];
+#pragma unroll
+      for (int i = 0; i < P2; ++i) pp[i] = 0.f;
+      // layer 3 one row block at a time; row block ob of the packed layer-2
+      // operands is half (ob % 2) of K step ob / 2
+      static_for<MB>([&](auto OB) {
+        constexpr int ob = decltype(OB)::value, tt = ob / 2, hh = ob % 2;
+        const bf16x8* aL = sA + (MB + ob) * SHB * 64 + lane;
+        bf16x2 jp[P][2], gJ[P][2], xs[P][2], xq[P][2];
         static_for<P>([&](auto MI) {
           constexpr int m = decltype(MI)::value;
-          bf16x2 h0 = (bf16x2){src[m][0][0], src[m][0][1]}, h1 = (bf16x2){src[m][0][2], src[m][0][3]};
+          f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int b = 1; b < MB; ++b) {
-            const int t = b / 2, e0 = 4 * (b % 2);
-            h0 = (ob == b) ? (bf16x2){src[m][t][e0], src[m][t][e0 + 1]} : h0;
-            h1 = (ob == b) ? (bf16x2){src[m][t][e0 + 2], src[m][t][e0 + 3]} : h1;
-          }
-          vp[m][0] = h0;
-          vp[m][1] = h1;
-          u2[m][0] = pk_bf16(wl[0] * bf16_to_f32(h0[0]), wl[1] * bf16_to_f32(h0[1]));
-          u2[m][1] = pk_bf16(wl[2] * bf16_to_f32(h1[0]), wl[3] * bf16_to_f32(h1[1]));
+          for (int t = 0; t < SHB; ++t) acc = mfma(aL[t * 64], src3[m][t], acc);
+          const f4 bv = row4(sBt + P * H + m * H, ob);
+          float J[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) J[v] = acc[v] + bv[v];
+          jp[m][0] = pk_bf16(J[0], J[1]);
+          jp[m][1] = pk_bf16(J[2], J[3]);
+          gJ[m][0] = pk_bf16(gm[1][ob][0] * J[0], gm[1][ob][1] * J[1]);
+          gJ[m][1] = pk_bf16(gm[1][ob][2] * J[2], gm[1][ob][3] * J[3]);
+          half_pairs(src3[m][tt], hh, xs[m][0], xs[m][1]);
+          half_pairs(q2[m][tt], hh, xq[m][0], xq[m][1]);
         });
-        add_pairs(u2, vp);
-      }
-    }
-    // last layer one row block at a time: every column of the block, then
-    // its Gram pairs
-#pragma unroll 1
-    for (int ob = 0; ob < MB; ++ob) {
-      float gl[4];  // gamma_L of row block ob
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        gl[v] = gm[L - 2][0][v];
-#pragma unroll
-        for (int b = 1; b < MB; ++b) gl[v] = (ob == b) ? gm[L - 2][b][v] : gl[v];
-      }
-      const bf16x8* aL = sA + ((L - 2) * MB + ob) * SHB * 64 + lane;
-      const float* bL = sBt + (L - 2) * P * H;
-      bf16x2 jp[P][2], gJ[P][2];  // J_L[ob, m] and gamma_L J_L[ob, m], packed
-      static_for<P>([&](auto MI) {
-        constexpr int m = decltype(MI)::value;
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < SHB; ++t) acc = mfma(aL[t * 64], src[m][t], acc);
-        const f4 bv = row4(bL + m * H, ob);
-        float J[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) J[v] = acc[v] + bv[v];
-        jp[m][0] = pk_bf16(J[0], J[1]);
-        jp[m][1] = pk_bf16(J[2], J[3]);
-        gJ[m][0] = pk_bf16(gl[0] * J[0], gl[1] * J[1]);
-        gJ[m][1] = pk_bf16(gl[2] * J[2], gl[3] * J[3]);
+        add_pairs(pp, gJ, jp);
+        add_pairs(pp, xq, xs);
       });
-      add_pairs(gJ, jp);
+      reduce_pairs(pp);
     }
     // lane group g holds pair 16 pb + 4 g + v
 #pragma unroll
