@@ -159,7 +159,18 @@ int run_inner(const pa_model_desc* d, const void* prepared, int prec, int64_t n,
     if (rc) return fail(PA_ERR_ARG, "bad inner-function configuration");
     return PA_OK;
   }
-  {
+  if (prec == PA_BF16_CORR && d->algorithm == PA_ALGO_ADJOINT) {
+    // the all-BF16 pass, then the FP32 pass that rewrites the value and
+    // gradient columns (the correction pass)
+    {
+      Prof pr("mlp_adjoint", s);
+      rc = launch_mlp(layout_of(d), PA_BF16, d->algorithm, (const unsigned char*)prepared, n, K, Nout, hess, s);
+    }
+    if (!rc) {
+      Prof pr("mlp_correction", s);
+      rc = launch_mlp(layout_of(d), PA_FP32, d->algorithm, (const unsigned char*)prepared, n, K, Nout, 0, s);
+    }
+  } else {
     Prof pr(d->algorithm == PA_ALGO_ADJOINT ? "mlp_adjoint" : "mlp_forward", s);
     rc = launch_mlp(layout_of(d), prec, d->algorithm, (const unsigned char*)prepared, n, K, Nout, hess, s);
   }

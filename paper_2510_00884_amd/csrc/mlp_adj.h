@@ -734,26 +734,15 @@ static void launch_bf16_one(const PrepLayout& lay, const unsigned char* prep, in
                                                                                                    out);
 }
 
-// FP32 value and gradient only (no Hessian): the correction pass of PREC_BF16C.
-template <int H, int L, int P>
-static void launch_fp32_grad(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
-                             double* out, hipStream_t s) {
-  if constexpr (L == 2 && H <= 32)
-    launch_adj2_one<H, P, PREC_F32, false>(lay, prep, n, K, out, s);
-  else
-    launch_adj_one<H, L, P, PREC_F32, false>(lay, prep, n, K, out, s);
-}
-
 template <int H, int L, int P>
 static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char* prep, int64_t n,
                             const double* K, double* out, int hess, hipStream_t s) {
-  // all-BF16 (two and three hidden layers), optionally followed by the FP32
-  // pass that rewrites the value and gradient columns
-  if (prec == PREC_BF16 || prec == PREC_BF16C) {
+  // all-BF16 (two and three hidden layers); PREC_BF16C is this pass
+  // followed by the FP32 value-and-gradient pass, launched by the caller
+  if (prec == PREC_BF16) {
     if constexpr (L <= 3) {
       if (hess) launch_bf16_one<H, L, P, true>(lay, prep, n, K, out, s);
       else launch_bf16_one<H, L, P, false>(lay, prep, n, K, out, s);
-      if (prec == PREC_BF16C) launch_fp32_grad<H, L, P>(lay, prep, n, K, out, s);
       return 0;
     } else {
       return -2;
