@@ -210,6 +210,19 @@ int pa_energy_stress_tangent(const pa_model_desc* desc, const void* prepared, in
                              double* AA, int32_t* n_bad, void* workspace, size_t ws_bytes,
                              void* stream);
 
+/* pa_energy_stress_tangent in batches of `batch` consecutive points (the
+ * batch-vectorised evaluation of Alg. 3 / Sec. 3.2): features, network and
+ * chain rule run on one batch at a time, so the workspace holds one batch,
+ * pa_material_workspace_bytes(desc, min(batch, n_qp)) bytes, however long
+ * the call.  F and the outputs are laid out as for pa_energy_stress_tangent
+ * ([..][n_qp]); every point's arithmetic is independent of the batch, so the
+ * outputs are bitwise the same for every batch size.  batch must be > 0
+ * (PA_ERR_ARG otherwise). */
+int pa_energy_stress_tangent_batched(const pa_model_desc* desc, const void* prepared, int prec,
+                                     int64_t n_qp, int64_t batch, const double* F, double* psi,
+                                     double* P, double* AA, int32_t* n_bad, void* workspace,
+                                     size_t ws_bytes, void* stream);
+
 /* Psi, Kirchhoff stress tau and spatial tangent cc at n_qp points, the
  * paper's own storage of the constitutive update (App. A.1-A.2, the tau and
  * cc of eqs. stress-cgo and stiffnes-cgo): tau [6][n_qp] and cc [21][n_qp]

@@ -64,6 +64,7 @@ SIGNATURES = {
     "pa_invariants": (C.c_int, [PDESC, I64, P, P, P, P, P]),
     "pa_material_workspace_bytes": (SZ, [PDESC, I64]),
     "pa_energy_stress_tangent": (C.c_int, [PDESC, P, C.c_int, I64, P, P, P, P, P, P, SZ, P]),
+    "pa_energy_stress_tangent_batched": (C.c_int, [PDESC, P, C.c_int, I64, I64, P, P, P, P, P, P, SZ, P]),
     "pa_energy_stress_tangent_noalloc": (C.c_int, [PDESC, P, C.c_int, I64, P, P, P, P, P, P]),
     "pa_noalloc_max_points": (I64, [PDESC]),
     "pa_mesh_geometry": (C.c_int, [I32, I64, I64, P, P, P, P, P, P]),

@@ -181,10 +181,12 @@ def invariants(model: Model, F, soa: bool = False):
 
 
 def energy_stress_tangent(model: Model, F, prec="fp64", psi=True, P=True, A=True, soa=False,
-                          n_bad=None, workspace=None, out=None, prepared=None):
+                          n_bad=None, workspace=None, out=None, prepared=None, batch=None):
     """Psi (n,), P (9, n), AA (81, n) in SoA layout (as returned by the
     library).  ``F`` is (n, 3, 3) or, with soa=True, (9, n).  ``prepared``:
-    a prepared-parameter buffer of this model (default: the model's own)."""
+    a prepared-parameter buffer of this model (default: the model's own).
+    ``batch``: evaluate in batches of that many points
+    (pa_energy_stress_tangent_batched; same outputs, workspace of one batch)."""
     Fs = F if soa else _soa9(F)
     n = Fs.shape[1]
     dev = Fs.device
@@ -201,10 +203,16 @@ def energy_stress_tangent(model: Model, F, prec="fp64", psi=True, P=True, A=True
     _need(out.get("P"), "P", 9 * n, device=model.device)
     _need(out.get("A"), "A", 81 * n, device=model.device)
     _need(n_bad, "n_bad", 1, torch.int32, device=model.device)
-    ws_bytes = model.lib.pa_material_workspace_bytes(C.byref(model.desc), n)
+    ws_bytes = model.lib.pa_material_workspace_bytes(C.byref(model.desc), n if batch is None else min(batch, n))
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
     prep = model.prepared if prepared is None else prepared
+    if batch is not None:
+        L.check(model.lib.pa_energy_stress_tangent_batched(
+            C.byref(model.desc), _p(prep), _prec(prec), n, int(batch), _p(Fs), _p(out.get("psi")),
+            _p(out.get("P")), _p(out.get("A")), _p(n_bad), _p(workspace), workspace.numel(), _stream()),
+            "pa_energy_stress_tangent_batched")
+        return out
     L.check(model.lib.pa_energy_stress_tangent(
         C.byref(model.desc), _p(prep), _prec(prec), n, _p(Fs), _p(out.get("psi")), _p(out.get("P")),
         _p(out.get("A")), _p(n_bad), _p(workspace), workspace.numel(), _stream()), "pa_energy_stress_tangent")
@@ -302,15 +310,32 @@ def voigt_unpack(tau, cc):
     return T, Cm
 
 
+def _morton3(q):
+    """Morton (Z-order) keys of non-negative integer triples q [n, 3] < 2^21."""
+    key = np.zeros(q.shape[0], dtype=np.uint64)
+    for b in range(21):
+        for d in range(3):
+            key |= ((q[:, d].astype(np.uint64) >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + d)
+    return key
+
+
 class FEMesh:
-    """Device-resident mesh: geometry, CSR pattern, element->CSR map and a
-    colouring.  Elements are renumbered colour by colour (``perm[i]`` is the
-    original id of element i) so every colour is a contiguous range.
+    """Device-resident mesh: geometry, CSR pattern, element->CSR map, node
+    incidence and a colouring.  ``perm[i]`` is the original id of element i.
+
+    order="colour": elements renumbered colour by colour, so every colour is
+    a contiguous range (needed by the fused coloured build).
+    order="morton": elements in the Z-order of their centroids, so elements
+    that share nodes are close in memory and in launch order (the node
+    gathers of the F pass and the element-table reads of the node-centric
+    assembly then hit the caches); the coloured assembly of element tables
+    walks the colours through ``elem_perm``.
+    order="native": elements as given.
     ``inline_geometry``: the tangent builds recompute shape gradients and
     weights from the node coordinates instead of reading the stored ones
     (same values, less memory traffic)."""
 
-    def __init__(self, X, conn, colour=None, device="cuda", inline_geometry=True):
+    def __init__(self, X, conn, colour=None, device="cuda", inline_geometry=True, order="colour"):
         self.lib = lib = L.load()
         X = np.ascontiguousarray(X, dtype=np.float64)
         conn = np.ascontiguousarray(conn, dtype=np.int32)
@@ -324,13 +349,28 @@ class FEMesh:
             L.check(lib.pa_colour_elements(nen, n_el, self.n_nodes, conn.ctypes.data_as(C.c_void_p),
                                            colour.ctypes.data_as(C.c_void_p), C.byref(nc)), "pa_colour_elements")
         colour = np.asarray(colour, dtype=np.int32)
-        self.perm = np.argsort(colour, kind="stable").astype(np.int64)
+        if order not in ("colour", "morton", "native"):
+            raise ValueError(f"unknown element order {order!r}")
+        self.order = order
+        if order == "colour":
+            self.perm = np.argsort(colour, kind="stable").astype(np.int64)
+        elif order == "morton" and n_el:
+            cen = X[conn].mean(axis=1)
+            lo, span = cen.min(axis=0), np.ptp(cen, axis=0).max()
+            qz = np.floor((cen - lo) / (span if span > 0 else 1.0) * ((1 << 20) - 1)).astype(np.int64)
+            self.perm = np.argsort(_morton3(qz), kind="stable").astype(np.int64)
+        else:
+            self.perm = np.arange(n_el, dtype=np.int64)
         self.conn_host = np.ascontiguousarray(conn[self.perm])
-        counts = np.bincount(colour, minlength=int(colour.max()) + 1 if n_el else 0)
+        mcol = colour[self.perm]  # colour of element i of the mesh
+        counts = np.bincount(mcol, minlength=int(mcol.max()) + 1 if n_el else 0)
         self.colour_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
         self.n_colours = len(counts)
         dev = _dev(device)
         self.device = dev
+        # elements of the mesh listed colour by colour (identity for order="colour")
+        self.elem_perm = None if order == "colour" else torch.tensor(
+            np.argsort(mcol, kind="stable").astype(np.int32), device=dev)
         self.X = torch.tensor(X.T.copy(), device=dev)
         self.conn = torch.tensor(self.conn_host.T.copy(), device=dev)
         self.dNdX = torch.empty((self.nq, nen, 3, n_el), dtype=torch.float64, device=dev)
@@ -356,7 +396,8 @@ class FEMesh:
                            self.e2csr.data_ptr())
         L.check(lib.pa_element_csr_map(C.byref(self.c_mesh), C.byref(self.c_csr), _p(self.e2csr), _stream()),
                 "pa_element_csr_map")
-        self.c_col = L.Colouring(self.n_colours, self.colour_ptr.ctypes.data_as(C.c_void_p).value, None)
+        self.c_col = L.Colouring(self.n_colours, self.colour_ptr.ctypes.data_as(C.c_void_p).value,
+                                 None if self.elem_perm is None else self.elem_perm.data_ptr())
         # node incidence for the gather assembly
         inc_ptr = np.empty(self.n_nodes + 1, dtype=np.int64)
         inc_ent = np.empty(n_el * nen, dtype=np.int32)
@@ -434,6 +475,8 @@ def tangent_build(model: Model, mesh: FEMesh, u, prec="fp64", workspace=None, bu
         r, vals = assemble_csr(mesh, r_e, K_e, r=bufs.get("r"), vals=bufs.get("vals"))
         bufs.update(r_e=r_e, K_e=K_e, r=r, vals=vals)
         return r, vals
+    if assembly == "coloured" and mesh.order != "colour":
+        raise ValueError("the fused coloured build needs a mesh numbered colour by colour (order='colour')")
     u = u.reshape(-1).contiguous()
     dev = u.device
     r = bufs.get("r")

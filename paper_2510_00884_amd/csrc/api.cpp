@@ -125,7 +125,9 @@ ModelConst model_const(const pa_model_desc* d) {
 inline int p_of(const pa_model_desc* d) { return 3 + 2 * npair_of(d->n_sv); }
 
 inline PrepLayout layout_of(const pa_model_desc* d) {
-  return prep_layout(padded_width(d->width), d->n_hidden, p_of(d));
+  PrepLayout l = prep_layout(padded_width(d->width), d->n_hidden, p_of(d));
+  l.HR = d->width;
+  return l;
 }
 
 inline int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
@@ -179,27 +181,38 @@ int run_inner(const pa_model_desc* d, const void* prepared, int prec, int64_t n,
   return PA_OK;
 }
 
-// F -> (psi, P, AA) through features, network and chain rule.
+// F -> (psi, P, AA) through features, network and chain rule, in batches of
+// `batch` consecutive points (batch <= 0: all n at once).  The workspace
+// holds one batch; F and the outputs keep their leading dimension n.  Each
+// point's arithmetic is independent of the batch, so the outputs are the
+// same for every batch size.
 int run_material(const pa_model_desc* d, const void* prepared, int prec, int64_t n, const double* F,
                  double* psi, double* P, double* A, int32_t* n_bad, unsigned char* ws, hipStream_t s,
-                 bool voigt = false) {
+                 bool voigt = false, int64_t batch = 0) {
   const int p = p_of(d);
   const ModelConst mc = model_const(d);
+  const int64_t nb = (batch <= 0 || batch > n) ? n : batch;
   double* K = (double*)ws;
-  double* Nout = (double*)(ws + al(8 * (int64_t)p * n));
-  {
-    Prof pr("features", s);
-    if (launch_features(d->n_sv, n, F, mc, K, n_bad, s)) return fail(PA_ERR_ARG, "bad n_sv");
-  }
-  int rc = run_inner(d, prepared, prec, n, K, Nout, A != nullptr, s);
-  if (rc) return rc;
+  double* Nout = (double*)(ws + al(8 * (int64_t)p * nb));
   const double* hdr = hdr_of(d, prepared);
-  if (voigt) {
-    Prof pr("chain_voigt", s);
-    if (launch_chain_voigt(d->n_sv, n, F, Nout, hdr, mc, psi, P, A, s)) return fail(PA_ERR_ARG, "bad n_sv");
-  } else {
-    Prof pr("chain", s);
-    if (launch_chain(d->n_sv, n, F, Nout, hdr, mc, psi, P, A, n_bad, s)) return fail(PA_ERR_ARG, "bad n_sv");
+  auto at = [](double* x, int64_t o) { return x ? x + o : nullptr; };
+  for (int64_t b = 0; b < n; b += nb) {
+    const int64_t cnt = (n - b < nb) ? n - b : nb;
+    {
+      Prof pr("features", s);
+      if (launch_features(d->n_sv, cnt, n, F + b, mc, K, n_bad, s)) return fail(PA_ERR_ARG, "bad n_sv");
+    }
+    int rc = run_inner(d, prepared, prec, cnt, K, Nout, A != nullptr, s);
+    if (rc) return rc;
+    if (voigt) {
+      Prof pr("chain_voigt", s);
+      if (launch_chain_voigt(d->n_sv, cnt, n, F + b, Nout, hdr, mc, at(psi, b), at(P, b), at(A, b), s))
+        return fail(PA_ERR_ARG, "bad n_sv");
+    } else {
+      Prof pr("chain", s);
+      if (launch_chain(d->n_sv, cnt, n, F + b, Nout, hdr, mc, at(psi, b), at(P, b), at(A, b), n_bad, s))
+        return fail(PA_ERR_ARG, "bad n_sv");
+    }
   }
   return hip_check("material kernels");
 }
@@ -297,6 +310,22 @@ int pa_energy_stress_tangent(const pa_model_desc* d, const void* prepared, int p
   if (!workspace || (int64_t)ws_bytes < material_ws(d, n))
     return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)material_ws(d, n));
   return run_material(d, prepared, prec, n, F, psi, P, A, n_bad, (unsigned char*)workspace, S(stream));
+}
+
+int pa_energy_stress_tangent_batched(const pa_model_desc* d, const void* prepared, int prec, int64_t n,
+                                     int64_t batch, const double* F, double* psi, double* P, double* A,
+                                     int32_t* n_bad, void* workspace, size_t ws_bytes, void* stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if ((rc = check_prec(prec))) return rc;
+  if (n < 0) return fail(PA_ERR_ARG, "n_qp < 0");
+  if (batch <= 0) return fail(PA_ERR_ARG, "batch must be positive (got %lld)", (long long)batch);
+  if (n == 0) return PA_OK;
+  if (!prepared || !F) return fail(PA_ERR_ARG, "prepared and F must be non-NULL");
+  const int64_t nb = batch < n ? batch : n;
+  if (!workspace || (int64_t)ws_bytes < material_ws(d, nb))
+    return fail(PA_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)material_ws(d, nb));
+  return run_material(d, prepared, prec, n, F, psi, P, A, n_bad, (unsigned char*)workspace, S(stream), false, nb);
 }
 
 int pa_energy_stress_tangent_voigt(const pa_model_desc* d, const void* prepared, int prec, int64_t n,

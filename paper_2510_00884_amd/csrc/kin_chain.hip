@@ -59,8 +59,10 @@ __global__ void __launch_bounds__(256) k_invariants(int64_t n, const double* __r
 
 // Network outputs in SoA: row 0 = N, rows 1..P = dN/dK_m, then the packed
 // upper triangle of d2N/dK_m dK_n (row-major, m <= n).
+// F and the outputs have leading dimension ld (>= n; a batch of a longer
+// call), the network outputs n.
 template <int NSV>
-__global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restrict__ F,
+__global__ void __launch_bounds__(256) k_chain(int64_t n, int64_t ld, const double* __restrict__ F,
                                                const double* __restrict__ Nout, const double* __restrict__ N0,
                                                ModelConst mc, double* __restrict__ psi,
                                                double* __restrict__ Pout, double* __restrict__ Aout,
@@ -70,7 +72,7 @@ __global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restri
   if (t >= n) return;
   double f[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = F[i * n + t];
+  for (int i = 0; i < 9; ++i) f[i] = F[i * ld + t];
   Kin k;
   kin_compute<NSV>(f, mc, k);
   if (psi) psi[t] = Nout[t] - N0[0];
@@ -82,8 +84,8 @@ __global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restri
   chain_material_stream<NSV>(k, mc, N1, N2, second, S, CCt);
   push_material(
       k, S, CCt,
-      [&](int c, double v) { if (Pout) Pout[(int64_t)c * n + t] = v; },
-      [&](int c, double v) { if (Aout) Aout[(int64_t)c * n + t] = v; });
+      [&](int c, double v) { if (Pout) Pout[(int64_t)c * ld + t] = v; },
+      [&](int c, double v) { if (Aout) Aout[(int64_t)c * ld + t] = v; });
   (void)n_bad;
 }
 
@@ -92,7 +94,7 @@ __global__ void __launch_bounds__(256) k_chain(int64_t n, const double* __restri
 // 6 x 6 matrix in TRI order: the paper's own storage of the constitutive
 // update (App. A.1-A.2), 216 instead of 720 bytes per point.
 template <int NSV>
-__global__ void __launch_bounds__(256) k_chain_voigt(int64_t n, const double* __restrict__ F,
+__global__ void __launch_bounds__(256) k_chain_voigt(int64_t n, int64_t ld, const double* __restrict__ F,
                                                      const double* __restrict__ Nout, const double* __restrict__ N0,
                                                      ModelConst mc, double* __restrict__ psi,
                                                      double* __restrict__ tau, double* __restrict__ cc) {
@@ -101,7 +103,7 @@ __global__ void __launch_bounds__(256) k_chain_voigt(int64_t n, const double* __
   if (t >= n) return;
   double f[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = F[i * n + t];
+  for (int i = 0; i < 9; ++i) f[i] = F[i * ld + t];
   Kin k;
   kin_compute<NSV>(f, mc, k);
   if (psi) psi[t] = Nout[t] - N0[0];
@@ -113,8 +115,8 @@ __global__ void __launch_bounds__(256) k_chain_voigt(int64_t n, const double* __
   chain_material_stream<NSV>(k, mc, N1, N2, second, S, CCt);
   push_spatial(
       k, S, CCt, second,
-      [&](int c, double v) { if (tau) tau[(int64_t)c * n + t] = v; },
-      [&](int c, double v) { cc[(int64_t)c * n + t] = v; });
+      [&](int c, double v) { if (tau) tau[(int64_t)c * ld + t] = v; },
+      [&](int c, double v) { cc[(int64_t)c * ld + t] = v; });
 }
 
 // dPsi/dC (6 slots) and d2Psi/dCdC (21 upper-triangle tensor components) per
@@ -145,14 +147,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 
 // Features only (input to the network kernels).
 template <int NSV>
-__global__ void __launch_bounds__(256) k_features(int64_t n, const double* __restrict__ F, ModelConst mc,
+__global__ void __launch_bounds__(256) k_features(int64_t n, int64_t ld, const double* __restrict__ F, ModelConst mc,
                                                   double* __restrict__ K, int32_t* n_bad) {
   constexpr int P = Feat<NSV>::P;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = t < n;
   double f[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = in ? F[i * n + t] : (i % 4 == 0 ? 1.0 : 0.0);
+  for (int i = 0; i < 9; ++i) f[i] = in ? F[i * ld + t] : (i % 4 == 0 ? 1.0 : 0.0);
   Kin k;
   kin_compute<NSV>(f, mc, k);
   count_bad(n_bad, in && !(k.J > 0.0 && finite9(f)));
@@ -178,13 +180,13 @@ int launch_invariants(int nsv, int64_t n, const double* F, const ModelConst& mc,
   return 0;
 }
 
-int launch_features(int nsv, int64_t n, const double* F, const ModelConst& mc, double* K,
+int launch_features(int nsv, int64_t n, int64_t ld, const double* F, const ModelConst& mc, double* K,
                     int32_t* n_bad, hipStream_t s) {
   if (n == 0) return 0;
   switch (nsv) {
-    case 0: k_features<0><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, K, n_bad); break;
-    case 1: k_features<1><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, K, n_bad); break;
-    case 2: k_features<2><<<nblk(n, 256), 256, 0, s>>>(n, F, mc, K, n_bad); break;
+    case 0: k_features<0><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, mc, K, n_bad); break;
+    case 1: k_features<1><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, mc, K, n_bad); break;
+    case 2: k_features<2><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, mc, K, n_bad); break;
     default: return -1;
   }
   return 0;
@@ -202,25 +204,25 @@ int launch_material_cc(int nsv, int64_t n, const double* F, const double* Nout, 
   return 0;
 }
 
-int launch_chain_voigt(int nsv, int64_t n, const double* F, const double* Nout, const double* N0,
+int launch_chain_voigt(int nsv, int64_t n, int64_t ld, const double* F, const double* Nout, const double* N0,
                        const ModelConst& mc, double* psi, double* tau, double* cc, hipStream_t s) {
   if (n == 0) return 0;
   switch (nsv) {
-    case 0: k_chain_voigt<0><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, tau, cc); break;
-    case 1: k_chain_voigt<1><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, tau, cc); break;
-    case 2: k_chain_voigt<2><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, tau, cc); break;
+    case 0: k_chain_voigt<0><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, Nout, N0, mc, psi, tau, cc); break;
+    case 1: k_chain_voigt<1><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, Nout, N0, mc, psi, tau, cc); break;
+    case 2: k_chain_voigt<2><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, Nout, N0, mc, psi, tau, cc); break;
     default: return -1;
   }
   return 0;
 }
 
-int launch_chain(int nsv, int64_t n, const double* F, const double* Nout, const double* N0,
+int launch_chain(int nsv, int64_t n, int64_t ld, const double* F, const double* Nout, const double* N0,
                  const ModelConst& mc, double* psi, double* P, double* A, int32_t* n_bad, hipStream_t s) {
   if (n == 0) return 0;
   switch (nsv) {
-    case 0: k_chain<0><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, P, A, n_bad); break;
-    case 1: k_chain<1><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, P, A, n_bad); break;
-    case 2: k_chain<2><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, N0, mc, psi, P, A, n_bad); break;
+    case 0: k_chain<0><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, Nout, N0, mc, psi, P, A, n_bad); break;
+    case 1: k_chain<1><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, Nout, N0, mc, psi, P, A, n_bad); break;
+    case 2: k_chain<2><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, Nout, N0, mc, psi, P, A, n_bad); break;
     default: return -1;
   }
   return 0;

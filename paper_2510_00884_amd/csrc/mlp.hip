@@ -34,7 +34,7 @@ static inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 PrepLayout prep_layout(int H, int L, int P) {
   PrepLayout l{};
-  l.H = H; l.L = L; l.P = P;
+  l.H = H; l.L = L; l.P = P; l.HR = H;
   l.MB = H / 16;
   l.S1 = (P + 3) / 4;
   l.SH = H / 4;
@@ -76,6 +76,8 @@ PrepLayout prep_layout(int H, int L, int P) {
     l.w_GT = take(16 * (int64_t)L * l.SHB * 64);
     l.w_G1 = take(16 * (int64_t)npb * l.SHB * 64);
   }
+  l.d_Am = take(8 * (int64_t)L * H * H);
+  l.f_Am = take(4 * (int64_t)L * H * H);
   l.k0 = take(8 * (int64_t)P * 16);
   l.nout = take(8 * (int64_t)l.NOUT * 16);
   l.total = o;
@@ -295,9 +297,18 @@ __global__ void k_prep_bf16(const double* __restrict__ th, ThetaLayout t, PrepLa
   __bf16* wGT = (__bf16*)(prep + l.w_GT);
   __bf16* wG1 = (__bf16*)(prep + l.w_G1);
   const int64_t nAT = (int64_t)L * MB * SHB * 512, nGT = (int64_t)L * SHB * 512, nG1 = (int64_t)NPB * SHB * 512;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nAT + nGT + nG1;
+  const int64_t nAm = (int64_t)L * H * H;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nAT + nGT + nG1 + nAm;
        idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = idx;
+    if (j >= nAT + nGT + nG1) {  // row-major A_k for the vector-ALU kernels: [k-1][r][q]
+      j -= nAT + nGT + nG1;
+      const int k = (int)(j / ((int64_t)H * H)) + 1, r = (int)((j / H) % H), q = (int)(j % H);
+      const double v = (k >= 2) ? th_w(th, t, k, r, q) : 0.0;
+      ((double*)(prep + l.d_Am))[j] = v;
+      ((float*)(prep + l.f_Am))[j] = (float)v;
+      continue;
+    }
     const int e = (int)(j % 8), lane = (int)((j / 8) % 64), i = lane & 15, g = lane >> 4;
     if (j < nAT) {  // [k-1][mb][tt][lane][e]: A_k[r][16 mb + i]
       const int tt = (int)((j / 512) % SHB), mb = (int)((j / (512 * SHB)) % MB), k = (int)(j / (512 * SHB * MB)) + 1;
@@ -377,6 +388,8 @@ int launch_mlp(const PrepLayout& lay, int prec, int algo, const unsigned char* p
   if (n == 0) return 0;
   if (algo == 1) {
     if (!mlp_supported(lay.H, lay.L, lay.P)) return -2;
+    // widths up to 8 in FP64 and FP32: one point per lane on the vector ALUs
+    if (lay.HR <= 8 && (prec == PREC_F64 || prec == PREC_F32)) return launch_mlp_valu(lay, prec, prep, n, K, out, hess, s);
     switch (lay.H) {
       case 16: return launch_mlp_adj_h16(lay, prec, prep, n, K, out, hess, s);
       case 32: return launch_mlp_adj_h32(lay, prec, prep, n, K, out, hess, s);

@@ -22,6 +22,7 @@ namespace pa {
 //   k0, nout: scratch used to evaluate the network at K = 0 (normalisation)
 struct PrepLayout {
   int32_t H, L, P, MB, S1, SH, SHB, NOUT;
+  int32_t HR;  // real width (H is the width of the zero-padded tables)
   int64_t hdr;
   int64_t d_a, d_b, d_c, d_W1t, d_Bt;
   int64_t f_a, f_c, f_W1t, f_Bt;
@@ -37,6 +38,7 @@ struct PrepLayout {
   int64_t w_AT;  // [L][MB][SHB]: lane (i, g) of row block mb holds A_k[neuron][16 mb + i]
   int64_t w_GT;  // [L][SHB]: row i = input: W1[neuron][i] (k = 1), B_k[neuron][i]
   int64_t w_G1;  // [NPB][SHB]: row i = packed pair 16 pb + i: W1[neuron][m] W1[neuron][n]
+  int64_t d_Am, f_Am;  // A_k row-major [L][H][H] (layer k at k - 1), FP64 and FP32
   int64_t k0, nout;
   int64_t total;
 };
@@ -80,13 +82,15 @@ ThetaLayout theta_layout(int H, int L, int P, int has_bias);
 // kinematics / chain (kin_chain.hip)
 int launch_invariants(int nsv, int64_t n, const double* F, const ModelConst& mc, double* I_raw,
                       double* K, double* dKdF, int32_t* n_bad, hipStream_t s);
-int launch_features(int nsv, int64_t n, const double* F, const ModelConst& mc, double* K,
+// F (and the outputs of the chain kernels) with leading dimension ld >= n:
+// n points of a batch of a longer call; K and Nout are [..][n].
+int launch_features(int nsv, int64_t n, int64_t ld, const double* F, const ModelConst& mc, double* K,
                     int32_t* n_bad, hipStream_t s);
 int launch_material_cc(int nsv, int64_t n, const double* F, const double* Nout, const ModelConst& mc,
                        double* SC, hipStream_t s);
-int launch_chain_voigt(int nsv, int64_t n, const double* F, const double* Nout, const double* N0,
+int launch_chain_voigt(int nsv, int64_t n, int64_t ld, const double* F, const double* Nout, const double* N0,
                        const ModelConst& mc, double* psi, double* tau, double* cc, hipStream_t s);
-int launch_chain(int nsv, int64_t n, const double* F, const double* Nout, const double* N0,
+int launch_chain(int nsv, int64_t n, int64_t ld, const double* F, const double* Nout, const double* N0,
                  const ModelConst& mc, double* psi, double* P, double* A, int32_t* n_bad, hipStream_t s);
 
 // network (mlp.hip)
@@ -105,6 +109,7 @@ PA_MLP_LAUNCHER(launch_mlp_fwd_h64)
 PA_MLP_LAUNCHER(launch_mlp_adj_h16)
 PA_MLP_LAUNCHER(launch_mlp_adj_h32)
 PA_MLP_LAUNCHER(launch_mlp_adj_h64)
+PA_MLP_LAUNCHER(launch_mlp_valu)
 #undef PA_MLP_LAUNCHER
 
 // parameter adjoint (adjoint.hip)

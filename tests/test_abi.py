@@ -222,3 +222,16 @@ def test_noalloc_limit_checked_before_launch(lib):
     assert rc == L.PA_ERR_ARG
     assert lib.pa_energy_stress_tangent_noalloc(C.byref(d), C.c_void_p(8), 0, 0, None, None, None, None, None,
                                                None) == L.PA_OK
+
+
+def test_batched_call_arguments_checked_before_launch(lib):
+    d = _desc(n_sv=2)
+    ws1 = lib.pa_material_workspace_bytes(C.byref(d), 1000)
+    rc = lib.pa_energy_stress_tangent_batched(C.byref(d), C.c_void_p(8), 0, 5000, 0, C.c_void_p(8), None, None,
+                                              None, None, C.c_void_p(8), ws1, None)
+    assert rc == L.PA_ERR_ARG
+    rc = lib.pa_energy_stress_tangent_batched(C.byref(d), C.c_void_p(8), 0, 5000, 1000, C.c_void_p(8), None,
+                                              None, None, None, C.c_void_p(8), ws1 - 1, None)
+    assert rc == L.PA_ERR_WORKSPACE
+    assert lib.pa_energy_stress_tangent_batched(C.byref(d), C.c_void_p(8), 0, 0, 1000, None, None, None, None,
+                                               None, None, 0, None) == L.PA_OK

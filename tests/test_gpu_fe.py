@@ -208,3 +208,39 @@ def test_single_cube_and_orphan_node(kind):
         assert np.all(r.cpu().numpy()[-3:] == 0.0)
     r_e, K_e = api.element_residual_stiffness(gm, mesh, ut, prec="fp64")
     close(K_e.cpu().numpy().transpose(2, 0, 1), K_ref, 1e-12, "K_e")
+
+
+@pytest.mark.parametrize("kind,n", [("hex8", 4), ("tet10", 2)])
+@pytest.mark.parametrize("order", ["native", "morton"])
+def test_element_orders(kind, n, order):
+    """Meshes numbered in the given order (native or Z-order of the element
+    centroids): the node-centric build equals the oracle's assembled residual
+    and tangent, and the element tables assembled colour by colour through
+    elem_perm equal the node-centric build; the fused coloured build refuses
+    a mesh not numbered colour by colour."""
+    api = need_gpu()
+    say("element order", kind, n, order)
+    X, conn, par = (synth.hex_mesh if kind == "hex8" else synth.tet10_mesh)(n)
+    n_sv, h, L = 2, 16, 2
+    p = synth.num_inputs(n_sv)
+    theta = synth.micnn_params(p, h, L, seed=1)
+    Av = synth.structural_vectors(n_sv)
+    gm = api.Model(theta, n_sv, h, L, A=Av, normalize=True, algorithm="adjoint")
+    om = ncm.model_from_theta(theta, p, h, L, Av, normalize=True)
+    mesh = api.FEMesh(X, conn, colour=par, order=order)
+    if order == "native":
+        assert np.array_equal(mesh.perm, np.arange(conn.shape[0]))
+    assert sorted(mesh.perm.tolist()) == list(range(conn.shape[0]))
+    u = synth.displacement_modes(X, 1.0 / n, seed=0)
+    ut = torch.tensor(u, device="cuda")
+    r, vals = api.tangent_build(gm, mesh, ut, prec="fp64", assembly="gather")
+    dNdX, w, _ = fe.geometry(X, conn)
+    r_ref, K_ref, _ = fe.element_residual_stiffness(u, conn, dNdX, w, om)
+    rg, Kg = fe.assemble(conn, r_ref, K_ref, X.shape[0])
+    close(r.cpu().numpy(), rg, 1e-12, "r")
+    close(vals.cpu().numpy(), Kg.data, 1e-12, "vals")
+    rt, vt = api.tangent_build(gm, mesh, ut, prec="fp64", assembly="coloured", fused=False)
+    close(rt.cpu().numpy(), r.cpu().numpy(), 1e-13, "tables + coloured assembly r")
+    close(vt.cpu().numpy(), vals.cpu().numpy(), 1e-13, "tables + coloured assembly vals")
+    with pytest.raises(ValueError):
+        api.tangent_build(gm, mesh, ut, prec="fp64", assembly="coloured", fused=True)

@@ -9,7 +9,8 @@ oracle, plus properties that hold at any size.
   BF16 with the FP32 correction pass;
 * 2^20-point stress calibration, 3x64, FP32 parameter adjoint;
 * tet10 Kuhn mesh of 56^3 cubes (1,053,696 elements, 4,328,691 dofs),
-  3x64 network in FP32, FP64 chain rule, elements and assembly.
+  3x64 network in FP64 and in FP32 (FP64 chain rule, elements and
+  assembly).
 
 Tolerances (normwise over the sample): FP64 1e-12; FP32 network 1e-5;
 BF16 2e-2 on Psi and P (1e-1 on the tangent); BF16 + correction 1e-4 on Psi
@@ -77,16 +78,27 @@ def compare_rows(ref, got, tol, what):
 
 
 def global_properties(mesh, r, vals, tol):
-    """The assembled tangent is symmetric and annihilates rigid translations."""
+    """The assembled tangent annihilates rigid translations and is symmetric.
+
+    Both hold for any network tangent (the shape gradients of an element sum
+    to zero; every element tangent has major symmetry), so only the FP64
+    rounding of the assembly enters: row i of K t is compared with
+    tol * (|K| |t|)_i, the rounding scale of that row's sum, and K - K^T with
+    tol * max |K|."""
     n = 3 * mesh.n_nodes
-    K = torch.sparse_csr_tensor(mesh.row_ptr, mesh.col.to(torch.int64), vals, size=(n, n))
+    ci = mesh.col.to(torch.int64)
+    K = torch.sparse_csr_tensor(mesh.row_ptr, ci, vals, size=(n, n))
+    Ka = torch.sparse_csr_tensor(mesh.row_ptr, ci, vals.abs(), size=(n, n))
     t = torch.tensor(np.tile([0.3, -1.1, 0.7], mesh.n_nodes), device=vals.device)
     Kt = K @ t
-    assert Kt.abs().max().item() <= tol * vals.abs().max().item() * 30
+    scale = Ka @ t.abs()
+    worst = (Kt.abs() / scale.clamp_min(1e-300)).max().item()
+    assert worst <= tol, f"translation null space: row residual {worst:.2e} of its rounding scale"
     Kc = K.to_sparse_coo().coalesce()
     KT = torch.sparse_coo_tensor(Kc.indices().flip(0), Kc.values(), size=(n, n)).coalesce()
     d = (Kc - KT).coalesce().values()
-    assert d.abs().max().item() <= tol * vals.abs().max().item() * 10
+    asym = d.abs().max().item() / vals.abs().max().item()
+    assert asym <= tol, f"asymmetry {asym:.2e}"
 
 
 def test_hex8_64_tangent_build():
@@ -206,9 +218,12 @@ def test_tet10_56_tangent_build():
     mesh = api.FEMesh(X, conn, colour=par)
     say("  mesh", mesh.n_el, "elements", 3 * mesh.n_nodes, "dofs", mesh.nnz, "nonzeros")
     ut = torch.tensor(u, device="cuda")
-    r, vals = api.tangent_build(gm, mesh, ut, prec="fp32", assembly="gather")
-    assert int(mesh.n_bad.item()) == 0
     nodes = synth.rng(14).choice(mesh.n_nodes, 24, replace=False)
     ref = oracle_rows(mesh, X, u, om, nodes)
-    compare_rows(ref, gpu_rows(mesh, r, vals, nodes), 1e-5, "tet10 fp32")
-    global_properties(mesh, r, vals, 1e-12)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        r, vals = api.tangent_build(gm, mesh, ut, prec=prec, assembly="gather")
+        assert int(mesh.n_bad.item()) == 0
+        compare_rows(ref, gpu_rows(mesh, r, vals, nodes), tol, f"tet10 {prec}")
+        global_properties(mesh, r, vals, 1e-13)
+        say(f"  tet10 {prec} ok")
+        del r, vals

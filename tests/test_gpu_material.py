@@ -97,6 +97,62 @@ def test_inverted_points_are_counted():
     close(A, ref["A"], 1e-12, "A")
 
 
+@pytest.mark.parametrize("prec,algorithm", [("fp64", "adjoint"), ("fp64", "forward"), ("fp32", "adjoint"),
+                                            ("bf16", "adjoint")])
+def test_singular_and_nonfinite_points(prec, algorithm):
+    """Points with J = 0 (F = diag(1.25, 0.75, 0) and F = 0, exactly singular
+    in binary), a NaN entry and an infinite entry: every one is counted in
+    n_bad and gets non-finite outputs; the other points of the same tiles
+    keep their values (checked against the oracle)."""
+    api = need_gpu()
+    say("singular/non-finite points", prec, algorithm)
+    gm, om = build(api, 2, 32, 2, True, algorithm=algorithm)
+    n = 64
+    F = synth.sample_F(n, seed=11)
+    bad = {3: np.diag([1.25, 0.75, 0.0]), 17: np.zeros((3, 3))}
+    F[3], F[17] = bad[3], bad[17]
+    F[20, 1, 2] = np.nan
+    F[40, 0, 0] = np.inf
+    bad_idx = [3, 17, 20, 40]
+    nb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec=prec, n_bad=nb)
+    assert int(nb.item()) == len(bad_idx)
+    psi, P, A = unpack(out, n)
+    for i in bad_idx:
+        assert not (np.isfinite(psi[i]) and np.isfinite(P[i]).all() and np.isfinite(A[i]).all()), i
+    good = np.setdiff1d(np.arange(n), bad_idx)
+    assert np.isfinite(psi[good]).all() and np.isfinite(P[good]).all() and np.isfinite(A[good]).all()
+    ref = ncm.stress_stiffness(F[good], om)
+    tol = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 2e-2}[prec]
+    close(P[good], ref["P"], tol, "P of the finite points")
+    close(A[good], ref["A"], tol if prec != "bf16" else 3e-2, "A of the finite points")
+
+
+def test_volumetric_feature_near_unit_jacobian():
+    """(J - 1)^2 at J within 1e-9 .. 1e-4 of 1, against its exact value: F
+    diagonal with binary-exact stretches, J - 1 evaluated in exact rational
+    arithmetic.  J - 1 computed as det F - 1 would lose up to seven digits
+    here; the kernels form it from H = F - I without cancellation."""
+    from fractions import Fraction
+    api = need_gpu()
+    say("volumetric feature near J = 1")
+    gm, _ = build(api, 0, 16, 2, False)
+    eps = [2.0 ** -30, -(2.0 ** -30), 2.0 ** -20, -(3.0 * 2.0 ** -25), 2.0 ** -14]
+    F = np.zeros((len(eps) * 3, 3, 3))
+    exact = []
+    for i, e in enumerate(eps):
+        for j, lam in enumerate([(1 + e, 1.0, 1.0), (1 + e, 1 - e, 1.0), (1 + e, 1 + e, 1 - 2 * e)]):
+            F[3 * i + j] = np.diag(lam)
+            jm1 = Fraction(lam[0]) * Fraction(lam[1]) * Fraction(lam[2]) - 1
+            exact.append(float(jm1 * jm1))
+    exact = np.array(exact)
+    keep = exact > 0
+    _, K, _ = api.invariants(gm, torch.tensor(F, device="cuda"))
+    got = K[2].cpu().numpy()
+    relerr = np.abs(got[keep] - exact[keep]) / exact[keep]
+    assert relerr.max() < 1e-12, relerr.max()
+
+
 @pytest.mark.parametrize("prec,tol_psi,tol_P,tol_A", [("fp32", 1e-5, 1e-5, 1e-5), ("bf16", 2e-2, 2e-2, 1e-1),
                                                       ("bf16_corr", 1e-4, 1e-4, 1e-1)])
 @pytest.mark.parametrize("n_sv,h,L", [(2, 32, 2), (2, 64, 3)])

@@ -1,7 +1,8 @@
 """GPU parity across network sizes outside the mesh configurations: widths
-below 16 (zero-padded to one 16-row matrix-core tile) and four hidden
-layers (adjoint form only), against the FP64 oracle on seeded inputs with
-full 16-point tiles and a ragged tail.  Tolerances (normwise): FP64 1e-12
+up to 8 (FP64 and FP32 on the vector ALUs, one point per lane; the BF16
+modes and the forward mode zero-padded to one 16-row matrix-core tile),
+widths 9..16 (padded) and four hidden layers, against the FP64 oracle on
+seeded inputs with full 16-point tiles and a ragged tail.  Tolerances (normwise): FP64 1e-12
 for Psi, P and the tangent, 1e-10 for the parameter adjoint; FP32 network
 1e-5 (tangent) and 1e-4 (parameter adjoint)."""
 import numpy as np
@@ -16,7 +17,8 @@ from gpu_util import close, need_gpu, rel, say
 pytestmark = pytest.mark.gpu
 
 # (n_sv, width, hidden layers)
-SIZES = [(2, 8, 2), (1, 4, 3), (0, 2, 2), (2, 16, 4), (1, 32, 4), (2, 64, 4)]
+SIZES = [(2, 8, 2), (1, 4, 3), (0, 2, 2), (2, 1, 2), (2, 5, 3), (1, 3, 2), (2, 8, 4), (2, 12, 2), (2, 16, 4),
+         (1, 32, 4), (2, 64, 4)]
 
 
 def build(api, n_sv, h, L, normalize=True, algorithm="adjoint", has_bias=True):
@@ -47,7 +49,7 @@ def test_adjoint_fp64_sizes(n_sv, h, L):
     close(A, ref["A"], 1e-12, "A")
 
 
-@pytest.mark.parametrize("n_sv,h,L", [(2, 8, 2), (2, 32, 4)])
+@pytest.mark.parametrize("n_sv,h,L", [(2, 8, 2), (2, 32, 4), (1, 2, 3), (2, 6, 4)])
 def test_adjoint_fp32_sizes(n_sv, h, L):
     api = need_gpu()
     say("sizes adjoint fp32", n_sv, h, L)
@@ -122,3 +124,23 @@ def test_tangent_build_depth4():
     r, vals = api.tangent_build(gm, mesh, torch.tensor(u, device="cuda"), prec="fp64")
     close(r.cpu().numpy(), rg, 1e-12, "r")
     close(vals.cpu().numpy(), Kg.data, 1e-12, "vals")
+
+
+@pytest.mark.parametrize("n_sv,h,L,prec", [(2, 32, 2, "fp64"), (2, 64, 3, "bf16"), (2, 8, 2, "fp32"),
+                                            (1, 16, 3, "fp32")])
+def test_batched_material_call_is_bitwise_batch_independent(n_sv, h, L, prec):
+    """pa_energy_stress_tangent_batched: batches of 1,000 (ragged: not a
+    multiple of the 16-point tile), 4,096 and 16,384 points give outputs
+    bitwise equal to the one-launch call, with a workspace of one batch."""
+    api = need_gpu()
+    say("batched material call", n_sv, h, L, prec)
+    gm, om, *_ = build(api, n_sv, h, L)
+    n = 40_000
+    Ft = torch.tensor(synth.sample_F(n, seed=21), device="cuda")
+    ref = api.energy_stress_tangent(gm, Ft, prec=prec)
+    for b in (1000, 4096, 16384, n + 7):
+        got = api.energy_stress_tangent(gm, Ft, prec=prec, batch=b)
+        for k in ("psi", "P", "A"):
+            assert torch.equal(got[k], ref[k]), (b, k)
+    with pytest.raises(PaError):
+        api.energy_stress_tangent(gm, Ft, prec=prec, batch=0)
