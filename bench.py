@@ -448,14 +448,94 @@ def bench_tet10(args):
     return out
 
 
+def bench_sizes(args):
+    """Model-size sweep of App. E: the constitutive update (Psi, P, AA) on
+    2^20 points for MICNN depths 2-4 x widths 2-64, the CANN and Gent-Thomas.
+    Widths up to 8 (FP64, FP32) run on the vector ALUs, wider ones on the
+    matrix cores; BF16 on the matrix cores for depths 2-3."""
+    import torch
+
+    from paper_2510_00884_amd import api, synth
+    n, n_sv = 1 << 20, 2
+    p = synth.num_inputs(n_sv)
+    Av = synth.structural_vectors(n_sv)
+    F = torch.tensor(synth.sample_F(n, seed=0), device="cuda")
+    steps, warmup = max(args.steps // 4, 3), 1
+    res = {}
+    cases = [("micnn", w_, l_) for l_ in (2, 3, 4) for w_ in (2, 4, 8, 16, 32, 64)] + [("cann", 0, 0),
+                                                                                      ("gent_thomas", 0, 0)]
+    for kind, w_, l_ in cases:
+        if kind == "micnn":
+            gm = api.Model(synth.micnn_params(p, w_, l_, seed=1), n_sv, w_, l_, A=Av, normalize=True,
+                           algorithm="adjoint")
+            tag, precs = f"micnn {l_}x{w_}", ("fp64", "fp32") + (("bf16",) if l_ <= 3 else ())
+        else:
+            th = synth.cann_params(p, seed=2) if kind == "cann" else synth.GENT_THOMAS
+            gm = api.Model(th, n_sv, A=Av, normalize=True, kind=kind)
+            tag, precs = kind, ("fp64",)
+        for prec in precs:
+            box = {}
+
+            def call():
+                box["o"] = api.energy_stress_tangent(gm, F, prec=prec, out=box.get("o"))
+            ms, kern = timed(call, steps, warmup)
+            e = {"params": gm.n_params, "ms": ms, "qp_per_s": n / (ms * 1e-3), "kernels": kern}
+            k = kern.get("mlp_adjoint")
+            if k:
+                fl = mlp_adjoint_flops(w_, l_, p) * n
+                if w_ <= 8 and prec != "bf16":  # vector-ALU kernel: its FLOPs against the vector peak
+                    e["network"] = "valu"
+                    t = k["ms_per_launch"] * 1e-3
+                    e["roofline"] = {"bound": "alu", "achieved": fl / t / 1e12, "peak": PEAK[prec] / 1e12,
+                                     "unit": "TFLOP/s", "frac": fl / t / PEAK[prec], "kernel": "mlp_adjoint",
+                                     "ms_per_launch": k["ms_per_launch"], "flop_per_launch": fl}
+                else:
+                    e["network"] = "mfma"
+                    e["roofline"] = network_roofline(kern, max(w_, 16), l_, p, prec, "adjoint", n)["network"]
+            res[f"{tag}/{prec}"] = e
+            say(f"sizes {tag} ({gm.n_params} params) {prec}: {ms:.3f} ms")
+    return {"workload": "model-size sweep (App. E): 2^20 independent points, orthotropic (9 inputs), Psi, P and "
+                        "dP/dF; MICNN 2-4 hidden layers x widths 2-64 (widths <= 8 in FP64/FP32 on the vector ALUs; "
+                        "the matrix-core roofline of widths below 16 counts the padded width 16), CANN, Gent-Thomas",
+            "n_points": n, "steps": steps, "models": res}
+
+
+def bench_batch(args):
+    """Batch-size sweep (Alg. 3 batches; the paper's optimal-batch study):
+    the 2^22-point 3x64 constitutive update in batches of 2^10 .. 2^22
+    points (pa_energy_stress_tangent_batched, workspace of one batch)."""
+    import torch
+
+    from paper_2510_00884_amd import api, synth
+    n, n_sv, h, Lh = 1 << 22, 2, 64, 3
+    p = synth.num_inputs(n_sv)
+    gm = api.Model(synth.micnn_params(p, h, Lh, seed=1), n_sv, h, Lh, A=synth.structural_vectors(n_sv),
+                   normalize=True, algorithm="adjoint")
+    F = torch.tensor(synth.sample_F(n, seed=0), device="cuda")
+    res = {}
+    for prec in ("fp64", "bf16"):
+        for lb in (10, 12, 14, 16, 18, 20, 22):
+            box = {}
+
+            def call():
+                box["o"] = api.energy_stress_tangent(gm, F, prec=prec, out=box.get("o"), batch=1 << lb)
+            ms, _ = timed(call, 2, 1)
+            res[f"{prec}/2^{lb}"] = {"batch": 1 << lb, "ms": ms, "qp_per_s": n / (ms * 1e-3),
+                                     "workspace_bytes": gm.lib.pa_material_workspace_bytes(
+                                         api.C.byref(gm.desc), 1 << lb)}
+            say(f"batch {prec} 2^{lb}: {ms:.3f} ms")
+    return {"workload": "2^22 points, MICNN 3x64, Psi + P + dP/dF evaluated in batches of 2^10 .. 2^22 points "
+                        "(outputs bitwise independent of the batch)", "n_points": n, "batches": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=64, help="cubes per side of the headline hex8 mesh")
-    ap.add_argument("--workloads", default="points,calib,tet10",
-                    help="other workloads carried in the line ('' for none): points, calib, tet10")
+    ap.add_argument("--workloads", default="points,calib,tet10,sizes,batch",
+                    help="other workloads carried in the line ('' for none): points, calib, tet10, sizes, batch")
     ap.add_argument("--variants", default="fp32,bf16,bf16_corr,bf16_jac,coloured",
                     help="headline-mesh variants after the FP64 build ('' for none)")
     ap.add_argument("--cpu-elements", type=int, default=2048,
@@ -561,7 +641,8 @@ def main():
 
     workloads = {}
     for wl in [w for w in args.workloads.split(",") if w]:
-        fn = {"points": bench_points, "calib": bench_calib, "tet10": bench_tet10}[wl]
+        fn = {"points": bench_points, "calib": bench_calib, "tet10": bench_tet10, "sizes": bench_sizes,
+              "batch": bench_batch}[wl]
         workloads[wl] = fn(args)
         torch.cuda.empty_cache()
 

@@ -13,8 +13,9 @@ oracle, plus properties that hold at any size.
   assembly).
 
 Tolerances (normwise over the sample): FP64 1e-12; FP32 network 1e-5;
-BF16 2e-2 on Psi and P (1e-1 on the tangent); BF16 + correction 1e-4 on Psi
-and P; FP32 parameter adjoint 1e-4."""
+BF16 2e-2 on Psi, P and the tangent; BF16 + correction 1e-4 on Psi and P
+(2e-2 on the tangent, which keeps the BF16 network Hessian); FP32
+parameter adjoint 1e-4."""
 import numpy as np
 import pytest
 import torch
@@ -133,8 +134,8 @@ def test_hex8_64_tangent_build():
     compare_rows(ref, gpu_rows(mesh, r32, v32, nodes), 1e-5, "gather fp32")
 
 
-PREC_TOL = [("fp64", 1e-12, 1e-12, 1e-12), ("fp32", 1e-5, 1e-5, 1e-5), ("bf16", 2e-2, 2e-2, 1e-1),
-            ("bf16_corr", 1e-4, 1e-4, 1e-1)]
+PREC_TOL = [("fp64", 1e-12, 1e-12, 1e-12), ("fp32", 1e-5, 1e-5, 1e-5), ("bf16", 2e-2, 2e-2, 2e-2),
+            ("bf16_corr", 1e-4, 1e-4, 2e-2)]
 
 
 def test_precision_ladder_2pow22_points():

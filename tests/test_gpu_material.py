@@ -3,8 +3,9 @@ against the FP64 oracle, element by element, on seeded inputs spanning
 several 16-point tiles and a ragged tail.
 
 Tolerances (normwise relative error over the batch): FP64 path 1e-12;
-FP32 network 1e-5; BF16 network 2e-2 on P; BF16 with the FP32 correction
-pass 1e-4 on P."""
+FP32 network 1e-5; BF16 network 2e-2 on Psi, P and the tangent; BF16 with
+the FP32 correction pass 1e-4 on Psi and P (the tangent keeps the BF16
+network Hessian: 2e-2)."""
 import numpy as np
 import pytest
 import torch
@@ -153,8 +154,8 @@ def test_volumetric_feature_near_unit_jacobian():
     assert relerr.max() < 1e-12, relerr.max()
 
 
-@pytest.mark.parametrize("prec,tol_psi,tol_P,tol_A", [("fp32", 1e-5, 1e-5, 1e-5), ("bf16", 2e-2, 2e-2, 1e-1),
-                                                      ("bf16_corr", 1e-4, 1e-4, 1e-1)])
+@pytest.mark.parametrize("prec,tol_psi,tol_P,tol_A", [("fp32", 1e-5, 1e-5, 1e-5), ("bf16", 2e-2, 2e-2, 2e-2),
+                                                      ("bf16_corr", 1e-4, 1e-4, 2e-2)])
 @pytest.mark.parametrize("n_sv,h,L", [(2, 32, 2), (2, 64, 3)])
 @pytest.mark.parametrize("algorithm", ["forward", "adjoint"])
 def test_precision_ladder(prec, tol_psi, tol_P, tol_A, n_sv, h, L, algorithm):
