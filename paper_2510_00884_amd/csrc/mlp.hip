@@ -78,6 +78,7 @@ PrepLayout prep_layout(int H, int L, int P) {
   }
   l.d_Am = take(8 * (int64_t)L * H * H);
   l.f_Am = take(4 * (int64_t)L * H * H);
+  l.x_AW = take(8 * (int64_t)P * l.MB * l.SH * 64);
   l.k0 = take(8 * (int64_t)P * 16);
   l.nout = take(8 * (int64_t)l.NOUT * 16);
   l.total = o;
@@ -297,10 +298,18 @@ __global__ void k_prep_bf16(const double* __restrict__ th, ThetaLayout t, PrepLa
   __bf16* wGT = (__bf16*)(prep + l.w_GT);
   __bf16* wG1 = (__bf16*)(prep + l.w_G1);
   const int64_t nAT = (int64_t)L * MB * SHB * 512, nGT = (int64_t)L * SHB * 512, nG1 = (int64_t)NPB * SHB * 512;
-  const int64_t nAm = (int64_t)L * H * H;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nAT + nGT + nG1 + nAm;
+  const int64_t nAm = (int64_t)L * H * H, nAW = (int64_t)P * MB * l.SH * 64;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nAT + nGT + nG1 + nAm + nAW;
        idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = idx;
+    if (j >= nAT + nGT + nG1 + nAm) {  // FP64 [m][ob][s = 4 mb + v][lane]: A_2[16 ob + i][q] W1[q][m]
+      j -= nAT + nGT + nG1 + nAm;
+      const int ln = (int)(j % 64), s = (int)((j / 64) % l.SH), ob = (int)((j / (64 * l.SH)) % MB);
+      const int m = (int)(j / (64 * l.SH * MB));
+      const int q = 16 * (s / 4) + row64(ln >> 4, s % 4), r = 16 * ob + (ln & 15);
+      ((double*)(prep + l.x_AW))[j] = (L >= 2) ? th_w(th, t, 2, r, q) * th_w(th, t, 1, q, m) : 0.0;
+      continue;
+    }
     if (j >= nAT + nGT + nG1) {  // row-major A_k for the vector-ALU kernels: [k-1][r][q]
       j -= nAT + nGT + nG1;
       const int k = (int)(j / ((int64_t)H * H)) + 1, r = (int)((j / H) % H), q = (int)(j % H);

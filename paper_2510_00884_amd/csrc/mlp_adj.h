@@ -30,6 +30,9 @@ namespace pa {
 //      products, and reduced four pairs at a time into the output tile.
 // Points on the N dimension, neurons split across waves as in k_mlp_fwd.
 
+// Softplus with the FP64 tables where the kernel holds them.
+__device__ inline void softplus3(float y, float& f, float& f1, float& f2, const SpTab&) { softplus3(y, f, f1, f2); }
+
 template <int H, int L, int P, int PR, bool HESS, bool PERSIST = !HESS>
 __global__ void __launch_bounds__(64 * (H / 16))
 k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
@@ -364,7 +367,7 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 // Jacobian feeds no later layer, so it is formed one row block at a time,
 // and the Hessian pairs are accumulated per wave in LDS and written once.
 template <int H, int P, int PR, bool HESS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(PR == PREC_F64 ? 512 : 256) __attribute__((amdgpu_waves_per_eu(2)))
 k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
            const double* __restrict__ Kin, double* __restrict__ out) {
   using E = typename std::conditional<PR == PREC_F64, EngF64, EngF32>::type;
@@ -373,19 +376,26 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   using frag_t = typename E::frag;
   constexpr int MB = H / 16, P2 = P * (P + 1) / 2;
   constexpr int SH = H / 4, S1 = (P + 3) / 4, NPB = (P2 + 15) / 16;
-  constexpr int WPB = 4;  // waves, one tile each, per workgroup
+  // FP64: the layer-2 and layer-1 matrix-core fragments are staged once per
+  // workgroup of eight waves, one tile each (LDS latency instead of L2
+  // latency on every tile), with the softplus tables and, for the Hessian,
+  // the layer-2 Jacobian column tables A_2 diag(W1[:, m]): a column is then
+  // the product of a constant table with F'(y_1), already in registers in
+  // K-step order.  FP32 reads the fragments from the prepared tables, four
+  // waves per workgroup, which leaves LDS for more resident waves.
+  constexpr bool LT = PR == PREC_F64;
+  constexpr bool AW = LT && HESS;
+  constexpr int WPB = LT ? 8 : 4;  // waves, one tile each, per workgroup
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
   const uint32_t g8 = 8u * (uint32_t)g;
 
   __shared__ T W1s[P][H], B2s[P][H], c1s[H], c2s[H], as_[H];
   __shared__ double db_s[P];
   __shared__ double hb[HESS ? WPB : 1][HESS ? P2 : 1][16];
-  // FP64: the layer-2 and layer-1 matrix-core fragments are staged once per
-  // workgroup (LDS latency instead of L2 latency on every tile); FP32 reads
-  // them from the prepared tables, which leaves LDS for more resident waves
-  constexpr bool LT = PR == PREC_F64;
+  __shared__ SpTab sp[1];
   constexpr int NW1 = MB * S1 * 64, NA2 = MB * SH * 64, NG1 = HESS ? NPB * MB * 4 * 64 : 1;
   __shared__ frag_t lW1[LT ? NW1 : 1], lA[LT ? NA2 : 1], lB[LT ? NW1 : 1], lATp[LT ? NA2 : 1], lG1[LT ? NG1 : 1];
+  __shared__ frag_t lAW[AW ? P * NA2 : 1];
 
   const bool dbl = std::is_same<T, double>::value;
   {
@@ -420,6 +430,11 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       }
       if constexpr (HESS)
         for (int i = tid; i < NG1; i += 64 * WPB) lG1[i] = gG1[i];
+      softplus_tab_fill(sp[0], tid, 64 * WPB);
+    }
+    if constexpr (AW) {
+      const frag_t* gAW = (const frag_t*)(prep + lay.x_AW);
+      for (int i = tid; i < P * NA2; i += 64 * WPB) lAW[i] = gAW[i];
     }
   }
   const frag_t* fW1 = LT ? lW1 : frag_ptr<E>(prep, lay, 0);
@@ -460,7 +475,8 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     for (int s = 0; s < S1; ++s) a1[s] = fW1[(mb * S1 + s) * 64 + lane];
     const acc_t acc = mma_in<E, P>(a1, kB, zero_acc<E>());
 #pragma unroll
-    for (int v = 0; v < 4; ++v) softplus3((T)(acc[v] + c1s[16 * mb + E::row(g, v)]), z1[mb][v], s1[mb][v], t1[mb][v]);
+    for (int v = 0; v < 4; ++v)
+      softplus3((T)(acc[v] + c1s[16 * mb + E::row(g, v)]), z1[mb][v], s1[mb][v], t1[mb][v], sp[0]);
   }
   // ---- layer 2, every row block; value, mu_2 = a F'(y_2), gamma_2 = a F''(y_2)
   T mu2[MB][4], gam2[MB][4];
@@ -477,7 +493,7 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * ob + E::row(g, v);
       T f, f1, f2;
-      softplus3((T)(acc[v] + c2s[r]), f, f1, f2);
+      softplus3((T)(acc[v] + c2s[r]), f, f1, f2, sp[0]);
       const T a = as_[r];
       val += (double)(a * f);
       mu2[ob][v] = a * f1;
@@ -549,13 +565,13 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       // else in this kernel is FP32
       constexpr bool JB = PR == PREC_BF16J;
       constexpr int SHB = (H + 31) / 32;
-      frag_t AV[JB ? 1 : SH];
+      frag_t AV[(JB || AW) ? 1 : SH];
       bf16x8 AZ[JB ? SHB : 1];
       if constexpr (JB) {
         const bf16x8* zA = frag_ptr<EngBF16>(prep, lay, 1);
 #pragma unroll
         for (int s = 0; s < SHB; ++s) AZ[s] = zA[((1 * MB + ob) * SHB + s) * 64 + lane];
-      } else {
+      } else if constexpr (!AW) {
 #pragma unroll
         for (int s = 0; s < SH; ++s) AV[s] = fA[(ob * SH + s) * 64 + lane];
       }
@@ -603,19 +619,30 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       };
       static_for<P>([&](auto MI) {
         constexpr int m = decltype(MI)::value;
-        T src[MB][4];
+        acc_t acc;  // starts from the skip column B_2[:, m]
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+        for (int v = 0; v < 4; ++v) acc[v] = B2s[m][16 * ob + E::row(g, v)];
+        if constexpr (AW) {
+          // column m = (A_2 diag(W1[:, m])) F'(y_1) + B_2[:, m]
+          const frag_t* aw = lAW + (m * MB + ob) * SH * 64 + lane;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) src[mb][v] = s1[mb][v] * W1s[m][16 * mb + E::row(g, v) + zr];
-        acc_t acc;
-        if constexpr (JB)
-          acc = mma_src<EngBF16, MB>(AZ, src, zero_acc<EngBF16>());
-        else
-          acc = mma_src<E, MB>(AV, src, zero_acc<E>());
+          for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc = E::mma(aw[(mb * 4 + v) * 64], (frag_t)s1[mb][v], acc);
+        } else {
+          T src[MB][4];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) src[mb][v] = s1[mb][v] * W1s[m][16 * mb + E::row(g, v) + zr];
+          if constexpr (JB)
+            acc = mma_src<EngBF16, MB>(AZ, src, acc);
+          else
+            acc = mma_src<E, MB>(AV, src, acc);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          Jc[v] = (T)acc[v] + B2s[m][16 * ob + E::row(g, v)];
+          Jc[v] = (T)acc[v];
           gJ[m][v] = g2[v] * Jc[v];
         }
         static_for<m + 1>([&](auto NI) { pair_sum(std::integral_constant<int, m * (m + 1) / 2 + decltype(NI)::value>{}); });
@@ -721,9 +748,10 @@ static void launch_adj_one(const PrepLayout& lay, const unsigned char* prep, int
 template <int H, int P, int PR, bool HESS>
 static void launch_adj2_one(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
                             double* out, hipStream_t s) {
-  const int64_t nblk = ((n + 15) / 16 + 3) / 4;
-  const unsigned grid = PR == PREC_F64 ? persistent_grid(k_mlp_adj2<H, P, PR, HESS>, 256, nblk) : (unsigned)nblk;
-  k_mlp_adj2<H, P, PR, HESS><<<grid, 256, 0, s>>>(prep, lay, n, K, out);
+  constexpr int WPB = PR == PREC_F64 ? 8 : 4, block = 64 * WPB;
+  const int64_t nblk = ((n + 15) / 16 + WPB - 1) / WPB;
+  const unsigned grid = PR == PREC_F64 ? persistent_grid(k_mlp_adj2<H, P, PR, HESS>, block, nblk) : (unsigned)nblk;
+  k_mlp_adj2<H, P, PR, HESS><<<grid, block, 0, s>>>(prep, lay, n, K, out);
 }
 
 template <int H, int L, int P, bool HESS>

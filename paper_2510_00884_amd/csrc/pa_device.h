@@ -136,6 +136,65 @@ __device__ inline void softplus3(float y, float& f, float& f1, float& f2) {
   f2 = e * r * r;
 }
 
+// FP64 softplus with two 64-entry tables, for kernels that fill them once
+// per workgroup (in LDS) and evaluate many activations:
+//   e^{-t} = 2^{-N/64} e^{-r},  N = rint(64 t / ln 2),  |r| <= ln 2 / 128,
+// with 2^{-j/64} from the table and e^{-r} from its Taylor polynomial to r^6
+// (first dropped term below 3e-20); the reduction t - N ln2/64 is exact in
+// its first fused step (|r| < 2^-7) and adds the low part of ln2/64 in a
+// second.  With j = floor(64 e) and a reciprocal w_j of the centre of the
+// j-th 64th of [1, 2] (w_0 = 1),
+//   log(1 + e) = -log w_j + log(1 + d),  d = (1 + e) w_j - 1 = e w_j + (w_j - 1),
+// where d comes from one fused multiply-add of exact operands (w_j - 1 is
+// exact), so it is correctly rounded for any stored w_j, and |d| < 1/64;
+// log(1 + d) from its series to d^9 (relative truncation below 1e-17).
+// F keeps its relative accuracy for large negative y (then j = 0, d = e).
+struct SpTab {
+  double e[64];   // 2^{-j/64}
+  double2 l[64];  // {w_j, -log w_j}
+};
+__device__ inline void softplus_tab_fill(SpTab& T, int tid, int nthreads) {
+  for (int j = tid; j < 64; j += nthreads) {
+    T.e[j] = exp2(-(double)j / 64.0);
+    const double w = (j == 0) ? 1.0 : 1.0 / (1.0 + ((double)j + 0.5) / 64.0);
+    T.l[j] = make_double2(w, -log(w));
+  }
+}
+__device__ inline void softplus3(double y, double& f, double& f1, double& f2, const SpTab& T) {
+  const double t = fmin(fabs(y), 745.5);  // e^{-745.5} is below half the smallest subnormal
+  const double kd = __builtin_rint(t * 92.33248261689366);  // 64 / ln 2
+  const int N = (int)kd;
+  double r = fma(-kd, 0x1.62e42fefa39efp-7, t);
+  r = fma(-kd, 0x1.abc9e3b39803fp-62, r);
+  const double x = -r;
+  double p = 1.0 / 720.0;
+  p = fma(p, x, 1.0 / 120.0);
+  p = fma(p, x, 1.0 / 24.0);
+  p = fma(p, x, 1.0 / 6.0);
+  p = fma(p, x, 0.5);
+  p = fma(p, x, 1.0);
+  p = fma(p, x, 1.0);
+  const double e = __builtin_ldexp(T.e[N & 63] * p, -(N >> 6));
+  const double u = 1.0 + e;
+  double rc = __builtin_amdgcn_rcp(u);
+  rc = fma(fma(-u, rc, 1.0), rc, rc);
+  rc = fma(fma(-u, rc, 1.0), rc, rc);
+  const double2 lw = T.l[min((int)(e * 64.0), 63)];
+  const double d = fma(e, lw.x, lw.x - 1.0);
+  double q = 1.0 / 9.0;
+  q = fma(q, d, -0.125);
+  q = fma(q, d, 1.0 / 7.0);
+  q = fma(q, d, -1.0 / 6.0);
+  q = fma(q, d, 0.2);
+  q = fma(q, d, -0.25);
+  q = fma(q, d, 1.0 / 3.0);
+  q = fma(q, d, -0.5);
+  q = fma(q, d, 1.0);
+  f = fmax(y, 0.0) + fma(q, d, lw.y);
+  f1 = (y >= 0.0) ? rc : e * rc;
+  f2 = e * rc * rc;
+}
+
 // Symmetric 3x3 tensors are stored as 6 tensor components in the order
 // 11, 22, 33, 23, 13, 12.  VI(I, J) maps a pair of indices to that slot.
 __device__ __host__ inline constexpr int VI(int I, int J) {
