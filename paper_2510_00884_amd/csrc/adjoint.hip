@@ -133,6 +133,11 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
   // outer-product update acc += U_p (16 x 16 points) * V_p^T (16 points x 16 cols).
   auto ufrag = [&](int p, int s) -> typename E::frag { return (typename E::frag)us[w][p][lane & 15][4 * s + g]; };
 
+  __shared__ SpTab sp[1];
+  if constexpr (std::is_same<T, double>::value) {
+    softplus_tab_fill(sp[0], tid, 64 * NW);
+    __syncthreads();
+  }
   const int64_t ntiles = (n + 15) / 16;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t base = tile * 16;
@@ -163,7 +168,7 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * mb + E::row(g, v);
         T f, f1, f2;
-        softplus3((T)(ay[v] + t_c[r]), f, f1, f2);
+        softplus3((T)(ay[v] + t_c[r]), f, f1, f2, sp[0]);
         z1[mb][v] = f; s1[mb][v] = f1; t1[mb][v] = f2;
         yd1[mb][v] = (T)ad[v];
         zd1[mb][v] = f1 * (T)ad[v];
@@ -200,7 +205,7 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * w + E::row(g, v);
         T f, f1, f2;
-        softplus3((T)(ay[v] + t_c[(k - 1) * H + r]), f, f1, f2);
+        softplus3((T)(ay[v] + t_c[(k - 1) * H + r]), f, f1, f2, sp[0]);
         sk[k - 2][v] = f1; tk[k - 2][v] = f2; ydk[k - 2][v] = (T)ad[v];
         const T zd = f1 * (T)ad[v];
         if constexpr (k < L) {

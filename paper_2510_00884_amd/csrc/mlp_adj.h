@@ -30,9 +30,6 @@ namespace pa {
 //      products, and reduced four pairs at a time into the output tile.
 // Points on the N dimension, neurons split across waves as in k_mlp_fwd.
 
-// Softplus with the FP64 tables where the kernel holds them.
-__device__ inline void softplus3(float y, float& f, float& f1, float& f2, const SpTab&) { softplus3(y, f, f1, f2); }
-
 template <int H, int L, int P, int PR, bool HESS, bool PERSIST = !HESS>
 __global__ void __launch_bounds__(64 * (H / 16))
 k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
@@ -100,7 +97,9 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   };
   for (int i = tid; i < L * H; i += 64 * NW) (&cs[0][0])[i] = t_c[i];
   for (int i = tid; i < H; i += 64 * NW) as_[i] = t_a[i];
-  __syncthreads();  // W1s, Bs, cs, as_
+  __shared__ SpTab sp[1];
+  if constexpr (std::is_same<T, double>::value) softplus_tab_fill(sp[0], tid, 64 * NW);
+  __syncthreads();  // W1s, Bs, cs, as_, sp
 
   const int64_t ntiles = (n + 15) / 16;
   auto tile_body = [&](int64_t tile) {
@@ -121,7 +120,7 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       for (int v = 0; v < 4; ++v) {
         T f, f1, f2;
         const int r = 16 * w + E::row(g, v);
-        softplus3((T)(acc[v] + cs[0][r]), f, f1, f2);
+        softplus3((T)(acc[v] + cs[0][r]), f, f1, f2, sp[0]);
         t1w[v] = f2;
         s1w[v] = f1;
         l1buf[0][r][q] = f;
@@ -157,7 +156,7 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           T f, f1, f2;
-          softplus3((T)(acc[v] + cs[k - 1][16 * w + E::row(g, v)]), f, f1, f2);
+          softplus3((T)(acc[v] + cs[k - 1][16 * w + E::row(g, v)]), f, f1, f2, sp[0]);
           sk[k - 2][v] = f1; tk[k - 2][v] = f2; o[v] = f;
         }
         if constexpr (k < L) {
@@ -473,10 +472,12 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     frag_t a1[S1];
 #pragma unroll
     for (int s = 0; s < S1; ++s) a1[s] = fW1[(mb * S1 + s) * 64 + lane];
-    const acc_t acc = mma_in<E, P>(a1, kB, zero_acc<E>());
+    acc_t acc;  // starts from the bias
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      softplus3((T)(acc[v] + c1s[16 * mb + E::row(g, v)]), z1[mb][v], s1[mb][v], t1[mb][v], sp[0]);
+    for (int v = 0; v < 4; ++v) acc[v] = c1s[16 * mb + E::row(g, v)];
+    acc = mma_in<E, P>(a1, kB, acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) softplus3((T)acc[v], z1[mb][v], s1[mb][v], t1[mb][v], sp[0]);
   }
   // ---- layer 2, every row block; value, mu_2 = a F'(y_2), gamma_2 = a F''(y_2)
   T mu2[MB][4], gam2[MB][4];
@@ -488,12 +489,15 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     for (int s = 0; s < SH; ++s) AV[s] = fA[(ob * SH + s) * 64 + lane];
 #pragma unroll
     for (int s = 0; s < S1; ++s) BV[s] = fB[(ob * S1 + s) * 64 + lane];
-    const acc_t acc = mma_in<E, P>(BV, kB, mma_src<E, MB>(AV, z1, zero_acc<E>()));
+    acc_t acc;  // starts from the bias
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = c2s[16 * ob + E::row(g, v)];
+    acc = mma_in<E, P>(BV, kB, mma_src<E, MB>(AV, z1, acc));
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * ob + E::row(g, v);
       T f, f1, f2;
-      softplus3((T)(acc[v] + c2s[r]), f, f1, f2, sp[0]);
+      softplus3((T)acc[v], f, f1, f2, sp[0]);
       const T a = as_[r];
       val += (double)(a * f);
       mu2[ob][v] = a * f1;

@@ -195,6 +195,9 @@ __device__ inline void softplus3(double y, double& f, double& f1, double& f2, co
   f2 = e * rc * rc;
 }
 
+// FP32 kernels share the call sites of the tabled FP64 form (no table).
+__device__ inline void softplus3(float y, float& f, float& f1, float& f2, const SpTab&) { softplus3(y, f, f1, f2); }
+
 // Symmetric 3x3 tensors are stored as 6 tensor components in the order
 // 11, 22, 33, 23, 13, 12.  VI(I, J) maps a pair of indices to that slot.
 __device__ __host__ inline constexpr int VI(int I, int J) {
