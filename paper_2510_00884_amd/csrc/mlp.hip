@@ -79,6 +79,8 @@ PrepLayout prep_layout(int H, int L, int P) {
   l.d_Am = take(8 * (int64_t)L * H * H);
   l.f_Am = take(4 * (int64_t)L * H * H);
   l.x_AW = take(8 * (int64_t)P * l.MB * l.SH * 64);
+  l.x_GT = take(8 * (int64_t)L * l.SH * 64);
+  l.y_GT = take(4 * (int64_t)L * l.SH * 64);
   l.k0 = take(8 * (int64_t)P * 16);
   l.nout = take(8 * (int64_t)l.NOUT * 16);
   l.total = o;
@@ -298,10 +300,24 @@ __global__ void k_prep_bf16(const double* __restrict__ th, ThetaLayout t, PrepLa
   __bf16* wGT = (__bf16*)(prep + l.w_GT);
   __bf16* wG1 = (__bf16*)(prep + l.w_G1);
   const int64_t nAT = (int64_t)L * MB * SHB * 512, nGT = (int64_t)L * SHB * 512, nG1 = (int64_t)NPB * SHB * 512;
-  const int64_t nAm = (int64_t)L * H * H, nAW = (int64_t)P * MB * l.SH * 64;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nAT + nGT + nG1 + nAm + nAW;
+  const int64_t nAm = (int64_t)L * H * H, nAW = (int64_t)P * MB * l.SH * 64, nXG = (int64_t)L * l.SH * 64;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nAT + nGT + nG1 + nAm + nAW + nXG;
        idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = idx;
+    if (j >= nAT + nGT + nG1 + nAm + nAW) {  // [k-1][s = 4 mb + v][lane]: W1[r][i] or B_k[r][i]
+      j -= nAT + nGT + nG1 + nAm + nAW;
+      const int ln = (int)(j % 64), s = (int)((j / 64) % l.SH), k = (int)(j / (64 * l.SH)) + 1;
+      const int i = ln & 15, gg = ln >> 4;
+      const int r64 = 16 * (s / 4) + row64(gg, s % 4), r32 = 16 * (s / 4) + row32(gg, s % 4);
+      double v64 = 0.0, v32 = 0.0;
+      if (i < P) {
+        v64 = (k == 1) ? th_w(th, t, 1, r64, i) : th_skip(th, t, k, r64, i);
+        v32 = (k == 1) ? th_w(th, t, 1, r32, i) : th_skip(th, t, k, r32, i);
+      }
+      ((double*)(prep + l.x_GT))[j] = v64;
+      ((float*)(prep + l.y_GT))[j] = (float)v32;
+      continue;
+    }
     if (j >= nAT + nGT + nG1 + nAm) {  // FP64 [m][ob][s = 4 mb + v][lane]: A_2[16 ob + i][q] W1[q][m]
       j -= nAT + nGT + nG1 + nAm;
       const int ln = (int)(j % 64), s = (int)((j / 64) % l.SH), ob = (int)((j / (64 * l.SH)) % MB);

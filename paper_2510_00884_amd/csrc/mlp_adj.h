@@ -688,6 +688,180 @@ k_mlp_adj2(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 }
 
 
+// ---------------------------------------------------------------- value and gradient, one wave per tile
+// Stress-only form (no Hessian) for any depth: one wave owns a 16-point tile
+// and every neuron, so the layers chain register to register (K steps in
+// accumulator-row order, as in k_mlp_adj2).  The reverse sweep runs on the
+// matrix cores twice over: lambda_{k-1} = A_k^T mu_k with the row-ordered
+// transposed weights, and the gradient b + W1^T mu_1 + sum_k B_k^T mu_k as
+// one accumulation whose result rows are the inputs (no cross-lane sums).
+// Every fragment table is staged once per workgroup of eight persistent
+// waves.  The LDS need (s1w_lds_bytes) decides where the launcher may use it.
+template <int H, int L, int P, int PR>
+__host__ __device__ constexpr int64_t s1w_lds_bytes() {
+  constexpr int64_t es = PR == PREC_F64 ? 8 : 4;
+  constexpr int64_t MB = H / 16, SH = H / 4, S1 = (P + 3) / 4;
+  return es * 64 * (MB * S1 + (L - 1) * MB * (2 * SH + S1) + L * SH) + es * (L + 1) * H + 8 * P +
+         (PR == PREC_F64 ? (int64_t)sizeof(SpTab) : 0);
+}
+
+template <int H, int L, int P, int PR>
+__global__ void __launch_bounds__(512) k_mlp_s1w(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
+                                                 const double* __restrict__ Kin, double* __restrict__ out) {
+  using E = typename std::conditional<PR == PREC_F64, EngF64, EngF32>::type;
+  using T = typename E::T;
+  using acc_t = typename E::acc;
+  using frag_t = typename E::frag;
+  constexpr int MB = H / 16, SH = H / 4, S1 = (P + 3) / 4, WPB = 8;
+  constexpr int NW1 = MB * S1 * 64, NA = MB * SH * 64, NB = MB * S1 * 64, NG = SH * 64;
+  static_assert(P <= 16, "the gradient rows are one 16-row block");
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
+  constexpr bool dbl = PR == PREC_F64;
+
+  __shared__ frag_t lW1[NW1], lA[L - 1][NA], lB[L - 1][NB], lAT[L - 1][NA], lG[L][NG];
+  __shared__ T cs[L][H], as_[H];
+  __shared__ double bs[P];
+  __shared__ SpTab sp[dbl ? 1 : 1];
+  {
+    const frag_t* gW1 = frag_ptr<E>(prep, lay, 0);
+    const frag_t* gA = frag_ptr<E>(prep, lay, 1);
+    const frag_t* gB = frag_ptr<E>(prep, lay, 2);
+    const frag_t* gAT = (const frag_t*)(prep + (dbl ? lay.x_ATp : lay.y_ATp));
+    const frag_t* gG = (const frag_t*)(prep + (dbl ? lay.x_GT : lay.y_GT));
+    for (int i = tid; i < NW1; i += 64 * WPB) lW1[i] = gW1[i];
+    // layer k >= 2 sits at index k - 1 of the per-layer tables
+    for (int i = tid; i < (L - 1) * NA; i += 64 * WPB) {
+      (&lA[0][0])[i] = gA[NA + i];
+      (&lAT[0][0])[i] = gAT[NA + i];
+    }
+    for (int i = tid; i < (L - 1) * NB; i += 64 * WPB) (&lB[0][0])[i] = gB[NB + i];
+    for (int i = tid; i < L * NG; i += 64 * WPB) (&lG[0][0])[i] = gG[i];
+    const T* t_c = (const T*)(prep + (dbl ? lay.d_c : lay.f_c));
+    const T* t_a = (const T*)(prep + (dbl ? lay.d_a : lay.f_a));
+    for (int i = tid; i < L * H; i += 64 * WPB) (&cs[0][0])[i] = t_c[i];
+    for (int i = tid; i < H; i += 64 * WPB) as_[i] = t_a[i];
+    for (int i = tid; i < P; i += 64 * WPB) bs[i] = ((const double*)(prep + lay.d_b))[i];
+    if constexpr (dbl) softplus_tab_fill(sp[0], tid, 64 * WPB);
+  }
+  __syncthreads();  // the only barrier: every wave reaches it before any exits
+
+  const int64_t ntiles = (n + 15) / 16;
+  auto load_k = [&](int64_t tile, double (&kv)[S1]) {
+    const int64_t qq = tile * 16 + q;
+#pragma unroll
+    for (int s = 0; s < S1; ++s) {
+      const int m = 4 * s + g;
+      kv[s] = (qq < n && m < P) ? Kin[(int64_t)m * n + qq] : 0.0;
+    }
+  };
+  auto tile_body = [&](int64_t tile, const double (&kin)[S1]) {
+    const int64_t qp = tile * 16 + q;
+    const bool valid = qp < n;
+    frag_t kB[S1];
+    double bK = 0.0;  // this lane's share of b . K, in FP64
+#pragma unroll
+    for (int s = 0; s < S1; ++s) {
+      const int m = 4 * s + g;
+      kB[s] = (T)kin[s];
+      if (m < P) bK += bs[m] * kin[s];
+    }
+    // ---- value forward; F'(y_k) of every layer kept
+    T z[MB][4], sk[L][MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      frag_t a1[S1];
+#pragma unroll
+      for (int s = 0; s < S1; ++s) a1[s] = lW1[(mb * S1 + s) * 64 + lane];
+      acc_t acc;  // starts from the bias
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = cs[0][16 * mb + E::row(g, v)];
+      acc = mma_in<E, P>(a1, kB, acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        T f2;
+        softplus3((T)acc[v], z[mb][v], sk[0][mb][v], f2, sp[0]);
+      }
+    }
+    double val = 0.0;
+    static_for<L - 1>([&](auto KI) {
+      constexpr int k = decltype(KI)::value + 2;
+      T zn[MB][4];
+#pragma unroll
+      for (int ob = 0; ob < MB; ++ob) {
+        frag_t AV[SH], BV[S1];
+#pragma unroll
+        for (int s = 0; s < SH; ++s) AV[s] = lA[k - 2][(ob * SH + s) * 64 + lane];
+#pragma unroll
+        for (int s = 0; s < S1; ++s) BV[s] = lB[k - 2][(ob * S1 + s) * 64 + lane];
+        acc_t acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = cs[k - 1][16 * ob + E::row(g, v)];
+        acc = mma_in<E, P>(BV, kB, mma_src<E, MB>(AV, z, acc));
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          T f2;
+          softplus3((T)acc[v], zn[ob][v], sk[k - 1][ob][v], f2, sp[0]);
+          if constexpr (k == L) val += (double)(as_[16 * ob + E::row(g, v)] * zn[ob][v]);
+        }
+      }
+      if constexpr (k < L) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) z[mb][v] = zn[mb][v];
+      }
+    });
+    val = group_sum(val) + group_sum(bK);
+    if (g == 0 && valid) out[qp] = val;
+    // ---- reverse: mu_L = a F'(y_L); gradient rows accumulate on the matrix cores
+    T mu[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mu[mb][v] = as_[16 * mb + E::row(g, v)] * sk[L - 1][mb][v];
+    acc_t gacc = zero_acc<E>();
+    static_for<L>([&](auto KI) {
+      constexpr int k = L - decltype(KI)::value;  // L, L-1, ..., 1
+#pragma unroll
+      for (int s = 0; s < SH; ++s) gacc = E::mma(lG[k - 1][s * 64 + lane], (frag_t)mu[s / 4][s % 4], gacc);
+      if constexpr (k >= 2) {
+        T mn[MB][4];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          acc_t acc = zero_acc<E>();
+#pragma unroll
+          for (int s = 0; s < SH; ++s) acc = E::mma(lAT[k - 2][(mb * SH + s) * 64 + lane], (frag_t)mu[s / 4][s % 4], acc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) mn[mb][v] = (T)acc[v] * sk[k - 2][mb][v];
+        }
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) mu[mb][v] = mn[mb][v];
+      }
+    });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = E::row(g, v);
+      if (c < P && valid) out[(int64_t)(1 + c) * n + qp] = (double)gacc[v] + bs[c];
+    }
+  };
+  // persistent waves: each takes every (gridDim.x * WPB)-th tile, the next
+  // tile's inputs in flight while the current one is computed
+  const int64_t stride = (int64_t)gridDim.x * WPB;
+  double kn[S1];
+  int64_t tile = (int64_t)blockIdx.x * WPB + w;
+  if (tile < ntiles) load_k(tile, kn);
+  for (; tile < ntiles; tile += stride) {
+    asm volatile("" ::: "memory");  // no fragment read is hoisted out of the tile loop
+    double kc[S1];
+#pragma unroll
+    for (int s = 0; s < S1; ++s) kc[s] = kn[s];
+    if (tile + stride < ntiles) load_k(tile + stride, kn);
+    tile_body(tile, kc);
+  }
+}
+
 // Persistent launch: as many workgroups as fit on the device at once (so the
 // per-workgroup set-up is paid once per resident group), never more than the
 // number of 16-point tiles.
@@ -758,6 +932,13 @@ static void launch_adj2_one(const PrepLayout& lay, const unsigned char* prep, in
   k_mlp_adj2<H, P, PR, HESS><<<grid, block, 0, s>>>(prep, lay, n, K, out);
 }
 
+template <int H, int L, int P, int PR>
+static void launch_s1w_one(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K, double* out,
+                           hipStream_t s) {
+  const int64_t nblk = ((n + 15) / 16 + 7) / 8;
+  k_mlp_s1w<H, L, P, PR><<<persistent_grid(k_mlp_s1w<H, L, P, PR>, 512, nblk), 512, 0, s>>>(prep, lay, n, K, out);
+}
+
 template <int H, int L, int P, bool HESS>
 static void launch_bf16_one(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
                             double* out, hipStream_t s) {
@@ -778,6 +959,18 @@ static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char
       return 0;
     } else {
       return -2;
+    }
+  }
+  // value and gradient only: one wave per tile with LDS-staged tables where
+  // they fit (FP64 three-layer width-64 networks keep the multi-wave kernel)
+  if (!hess && (prec == PREC_F32 || prec == PREC_BF16J)) {
+    launch_s1w_one<H, L, P, PREC_F32>(lay, prep, n, K, out, s);
+    return 0;
+  }
+  if constexpr (s1w_lds_bytes<H, L, P, PREC_F64>() <= 160 * 1024) {
+    if (!hess && prec == PREC_F64) {
+      launch_s1w_one<H, L, P, PREC_F64>(lay, prep, n, K, out, s);
+      return 0;
     }
   }
   if constexpr (L == 2 && H <= 32) {

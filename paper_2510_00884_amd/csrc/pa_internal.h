@@ -39,6 +39,8 @@ struct PrepLayout {
   int64_t w_GT;  // [L][SHB]: row i = input: W1[neuron][i] (k = 1), B_k[neuron][i]
   int64_t w_G1;  // [NPB][SHB]: row i = packed pair 16 pb + i: W1[neuron][m] W1[neuron][n]
   int64_t d_Am, f_Am;  // A_k row-major [L][H][H] (layer k at k - 1), FP64 and FP32
+  int64_t x_GT, y_GT;  // gradient products [L][SH][64], lane (i, g) of step s = 4 mb + v: W1[r][i] (layer 1)
+                       // or B_k[r][i], r = 16 mb + row(g, v) (row64 for x_, row32 for y_), zero for i >= P
   int64_t x_AW;        // FP64 [P][MB][SH][64]: layer-2 Jacobian column tables A_2 diag(W1[:, m]),
                        // lane (i, g) of step s = 4 mb + v: A_2[16 ob + i][q] W1[q][m], q = 16 mb + g + 4 v
   int64_t k0, nout;

@@ -282,9 +282,13 @@ def test_voigt_spatial_outputs(n_sv, h, L, normalize, prec, tol):
     e = (rel(out["psi"].cpu().numpy(), ref["psi"]), rel(tau, ref["tau"]), rel(cc, ref["cc"]))
     say("  errors psi/tau/cc", e)
     assert max(e) < tol
-    # stress only: no tangent, same tau
+    # stress only: no tangent, same tau (the value-and-gradient kernel orders
+    # its FP32 sums differently from the Hessian kernel, so FP32 agrees to
+    # its rounding, and both meet the oracle tolerance)
     out2 = api.energy_stress_tangent_voigt(gm, torch.tensor(F, device="cuda"), prec=prec, cc=False, psi=False)
-    close(out2["tau"].cpu().numpy(), out["tau"].cpu().numpy(), 1e-14, "tau without tangent")
+    close(out2["tau"].cpu().numpy(), out["tau"].cpu().numpy(), 1e-14 if prec == "fp64" else 1e-6, "tau without tangent")
+    tau2, _ = api.voigt_unpack(out2["tau"], out["cc"])
+    close(tau2, ref["tau"], tol, "tau without tangent vs oracle")
 
 
 @pytest.mark.parametrize("kind", ["cann", "gent_thomas"])

@@ -144,3 +144,29 @@ def test_batched_material_call_is_bitwise_batch_independent(n_sv, h, L, prec):
             assert torch.equal(got[k], ref[k]), (b, k)
     with pytest.raises(PaError):
         api.energy_stress_tangent(gm, Ft, prec=prec, batch=0)
+
+
+@pytest.mark.parametrize("n_sv,h,L", [(2, 16, 2), (2, 32, 2), (1, 32, 3), (2, 64, 2), (2, 64, 3), (2, 64, 4), (0, 16, 4)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16_corr"])
+def test_stress_only_sizes(n_sv, h, L, prec):
+    """Value and gradient without the tangent (the one-wave stress kernel, and
+    the FP32 pass of BF16 + correction) against the FP64 oracle, 2,000 points
+    (125 full tiles) plus a ragged tail of 7: FP64 1e-12 on Psi and P; FP32
+    and the corrected BF16 run 1e-5 (their value and gradient come from the
+    FP32 pass)."""
+    api = need_gpu()
+    say("sizes stress-only", prec, n_sv, h, L)
+    gm, om, *_ = build(api, n_sv, h, L)
+    n = 2007
+    F = synth.sample_F(n, seed=11)
+    if prec == "bf16_corr" and L > 3:  # the all-BF16 pass serves two and three hidden layers
+        with pytest.raises(PaError):
+            api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec=prec, A=False)
+        return
+    out = api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec=prec, A=False)
+    psi, P = out["psi"].cpu().numpy(), out["P"].cpu().numpy().T.reshape(n, 3, 3)
+    ref = ncm.stress_stiffness(F, om)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    e = (rel(psi, ref["psi"]), rel(P, ref["P"]))
+    say("  errors psi/P", e)
+    assert max(e) < tol
