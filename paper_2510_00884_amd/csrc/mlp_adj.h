@@ -6,6 +6,7 @@
 #include <utility>
 
 #include "mlp_bf16.h"
+#include "mlp_f32w.h"
 #include "mma_util.h"
 #include "pa_internal.h"
 
@@ -939,6 +940,13 @@ static void launch_s1w_one(const PrepLayout& lay, const unsigned char* prep, int
   k_mlp_s1w<H, L, P, PR><<<persistent_grid(k_mlp_s1w<H, L, P, PR>, 512, nblk), 512, 0, s>>>(prep, lay, n, K, out);
 }
 
+template <int H, int L, int P>
+static void launch_f32w_one(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
+                            double* out, hipStream_t s) {
+  const int64_t nblk = ((n + 15) / 16 + 3) / 4;
+  k_mlp_f32w<H, L, P><<<persistent_grid(k_mlp_f32w<H, L, P>, 256, nblk), 256, 0, s>>>(prep, lay, n, K, out);
+}
+
 template <int H, int L, int P, bool HESS>
 static void launch_bf16_one(const PrepLayout& lay, const unsigned char* prep, int64_t n, const double* K,
                             double* out, hipStream_t s) {
@@ -966,6 +974,14 @@ static int launch_mlp_adj_t(const PrepLayout& lay, int prec, const unsigned char
   if (!hess && (prec == PREC_F32 || prec == PREC_BF16J)) {
     launch_s1w_one<H, L, P, PREC_F32>(lay, prep, n, K, out, s);
     return 0;
+  }
+  // FP32 with the Hessian, three hidden layers: one wave per tile (with two
+  // layers the two-layer kernel below, several waves per SIMD, is faster)
+  if constexpr (L == 3) {
+    if (hess && prec == PREC_F32) {
+      launch_f32w_one<H, L, P>(lay, prep, n, K, out, s);
+      return 0;
+    }
   }
   if constexpr (s1w_lds_bytes<H, L, P, PREC_F64>() <= 160 * 1024) {
     if (!hess && prec == PREC_F64) {
