@@ -317,3 +317,35 @@ def test_closed_inner_functions(kind, n_sv, normalize):
     tau, cc = api.voigt_unpack(vo["tau"], vo["cc"])
     close(tau, ref["tau"], 1e-12, "tau")
     close(cc, ref["cc"], 1e-12, "cc")
+
+
+@pytest.mark.parametrize("algorithm", ["adjoint", "forward"])
+@pytest.mark.parametrize("n_sv,h,L", [(2, 32, 2), (2, 64, 3)])
+def test_large_preactivations_fp64(algorithm, n_sv, h, L):
+    """Hidden biases ~ N(0, 300), so the pre-activations of every layer span
+    hundreds in both signs: the softplus and its derivatives at their far
+    tails (e^{-|y|} down to underflow, F ~ y, F' ~ 0 or 1, F'' ~ 0), in the
+    kernels' own softplus (tabled in the adjoint form), against the oracle's
+    max(y, 0) + log1p(e^{-|y|}) at 1e-12."""
+    api = need_gpu()
+    say("large pre-activations", algorithm, n_sv, h, L)
+    p = synth.num_inputs(n_sv)
+    theta = synth.micnn_params(p, h, L, seed=3)
+    r = np.random.default_rng(7)
+    o = h * p  # theta layout: W1, c1, then per layer k >= 2: A_k, B_k, c_k; then a, b
+    theta[o:o + h] = r.normal(0.0, 300.0, h)
+    o += h
+    for _ in range(2, L + 1):
+        o += h * h + h * p
+        theta[o:o + h] = r.normal(0.0, 300.0, h)
+        o += h
+    Av = synth.structural_vectors(n_sv)
+    gm = api.Model(theta, n_sv, h, L, A=Av, normalize=True, algorithm=algorithm)
+    om = ncm.model_from_theta(theta, p, h, L, Av, normalize=True)
+    n = 1003
+    F = synth.sample_F(n, seed=8)
+    psi, P, A = unpack(api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec="fp64"), n)
+    ref = ncm.stress_stiffness(F, om)
+    close(psi, ref["psi"], 1e-12, "psi")
+    close(P, ref["P"], 1e-12, "P")
+    close(A, ref["A"], 1e-12, "A")

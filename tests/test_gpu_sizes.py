@@ -49,7 +49,7 @@ def test_adjoint_fp64_sizes(n_sv, h, L):
     close(A, ref["A"], 1e-12, "A")
 
 
-@pytest.mark.parametrize("n_sv,h,L", [(2, 8, 2), (2, 32, 4), (1, 2, 3), (2, 6, 4)])
+@pytest.mark.parametrize("n_sv,h,L", [(2, 8, 2), (2, 32, 4), (1, 2, 3), (2, 6, 4), (2, 64, 3), (1, 32, 3), (0, 16, 3)])
 def test_adjoint_fp32_sizes(n_sv, h, L):
     api = need_gpu()
     say("sizes adjoint fp32", n_sv, h, L)
