@@ -291,8 +291,10 @@ __global__ void k_prep_frags(const double* __restrict__ th, ThetaLayout t, PrepL
 // order of the previous product's result).
 __device__ inline int kperm_row(int t, int g, int e) { return e < 4 ? 32 * t + 4 * g + e : 32 * t + 16 + 4 * g + e - 4; }
 
-// Fragments of the all-BF16 adjoint form (layout in PrepLayout::w_*).
-__global__ void k_prep_bf16(const double* __restrict__ th, ThetaLayout t, PrepLayout l,
+// Tables of the one-wave-per-tile kernels: the all-BF16 fragments (w_*),
+// row-major A_k for the vector-ALU kernels (d_Am, f_Am), the FP64 layer-2
+// Jacobian column tables (x_AW) and the gradient tables (x_GT, y_GT).
+__global__ void k_prep_onewave(const double* __restrict__ th, ThetaLayout t, PrepLayout l,
                             unsigned char* __restrict__ prep) {
   const int H = l.H, P = l.P, L = l.L, MB = l.MB, SHB = l.SHB;
   const int P2 = P * (P + 1) / 2, NPB = (P2 + 15) / 16;
@@ -435,7 +437,7 @@ int launch_prepare(const PrepLayout& lay, const ThetaLayout& tl, const double* t
                    unsigned char* prep, int normalize, int npair, hipStream_t s) {
   k_prep_tables<<<64, 256, 0, s>>>(theta, tl, lay, prep);
   k_prep_frags<<<256, 256, 0, s>>>(theta, tl, lay, prep);
-  k_prep_bf16<<<64, 256, 0, s>>>(theta, tl, lay, prep);
+  k_prep_onewave<<<64, 256, 0, s>>>(theta, tl, lay, prep);
   if (normalize) {
     const int algo = mlp_fwd_supported(lay.H, lay.L, lay.P) ? 0 : 1;
     int rc = launch_mlp(lay, PREC_F64, algo, prep, 1, (const double*)(prep + lay.k0),

@@ -41,7 +41,10 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   using frag_t = typename E::frag;
   constexpr int MB = H / 16, NW = MB, P2 = P * (P + 1) / 2, NOUT = 1 + P + P2;
   constexpr int SH = H / 4, S1 = (P + 3) / 4, NPB = (P2 + 15) / 16;
-  constexpr int CH = (L >= 3) ? 3 : 1;  // gradient columns per LDS exchange chunk
+  // Jacobian columns per LDS exchange (two barriers each): all of them for
+  // the FP64 3 x 64 network, where one workgroup fills a CU anyway; three
+  // otherwise
+  constexpr int CH = (L >= 3) ? ((L == 3 && H >= 64 && PR == PREC_F64) ? P : 3) : 1;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane & 15, g = lane >> 4;
 
   __shared__ T W1s[P][H];          // W1^T
