@@ -93,6 +93,23 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 #pragma unroll
       for (int s = 0; s < SHB; ++s) AZ[k - 2][s] = zA[(((k - 1) * MB + w) * SHB + s) * 64 + lane];
   }
+  // this wave's layer-1 Gram and reverse-product fragments, the same for
+  // every tile, held in registers where the budget allows (no L2 latency in
+  // the tile loop)
+  constexpr bool HAT = HESS && (L - 1) * SH <= 32;
+  frag_t g1f[HESS ? NPB : 1][4], atf[HAT ? L - 1 : 1][HAT ? SH : 1];
+  if constexpr (HESS) {
+#pragma unroll
+    for (int pb = 0; pb < NPB; ++pb)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) g1f[pb][s] = fG1[((pb * MB + w) * 4 + s) * 64 + lane];
+  }
+  if constexpr (HAT) {
+#pragma unroll
+    for (int k = 2; k <= L; ++k)
+#pragma unroll
+      for (int s = 0; s < SH; ++s) atf[k - 2][s] = fAT[(((k - 1) * MB + w) * SH + s) * 64 + lane];
+  }
   auto jac_product = [&](int kk, const T (&src)[MB][4]) -> acc_t {
     if constexpr (JB)
       return mma_src<EngBF16, MB>(AZ[kk], src, zero_acc<EngBF16>());
@@ -102,19 +119,32 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   for (int i = tid; i < L * H; i += 64 * NW) (&cs[0][0])[i] = t_c[i];
   for (int i = tid; i < H; i += 64 * NW) as_[i] = t_a[i];
   __shared__ SpTab sp[1];
+  __shared__ double bs[P];
+  for (int i = tid; i < P; i += 64 * NW) bs[i] = d_b[i];
   if constexpr (std::is_same<T, double>::value) softplus_tab_fill(sp[0], tid, 64 * NW);
-  __syncthreads();  // W1s, Bs, cs, as_, sp
+  __syncthreads();  // W1s, Bs, cs, as_, bs, sp
 
   const int64_t ntiles = (n + 15) / 16;
-  auto tile_body = [&](int64_t tile) {
+  // this lane's inputs of a tile: feature 4 s + g of point q
+  auto load_k = [&](int64_t tile, double (&kv)[S1]) {
+    const int64_t qq = tile * 16 + q;
+#pragma unroll
+    for (int s = 0; s < S1; ++s) {
+      const int m = 4 * s + g;
+      kv[s] = (qq < n && m < P) ? Kin[(int64_t)m * n + qq] : 0.0;
+    }
+  };
+  auto tile_body = [&](int64_t tile, const double (&kin)[S1]) {
     const int64_t base = tile * 16;
     const int64_t qp = base + q;
     const bool valid = qp < n;
     frag_t kB[S1];
+    double bK = 0.0;  // this lane's share of b . K, in FP64 (added by wave 0)
 #pragma unroll
     for (int s = 0; s < S1; ++s) {
       const int m = 4 * s + g;
-      kB[s] = (valid && m < P) ? (T)Kin[(int64_t)m * n + qp] : (T)0;
+      kB[s] = (T)kin[s];
+      if (m < P) bK += bs[m] * kin[s];
     }
     // layer 1: own rows, then z_1 and F'(y_1) of every row through LDS
     T t1w[4], s1w[4], z1[MB][4];
@@ -171,6 +201,7 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
 #pragma unroll
           for (int v = 0; v < 4; ++v) pl += (double)(as_[16 * w + E::row(g, v)] * o[v]);
           pl = group_sum(pl);
+          if (w == 0) pl += group_sum(bK);
           if (g == 0) outp[w][0][q] = pl;
         }
       });
@@ -194,7 +225,12 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       const frag_t* at = fAT + (((k - 1) * MB + w) * SH) * 64 + lane;
       acc_t acc = zero_acc<E>();
 #pragma unroll
-      for (int s = 0; s < SH; ++s) acc = E::mma(at[s * 64], (frag_t)xbuf[0][4 * s + g][q], acc);
+      for (int s = 0; s < SH; ++s) {
+        frag_t a;
+        if constexpr (HAT) a = atf[k - 2][s];
+        else a = at[s * 64];
+        acc = E::mma(a, (frag_t)xbuf[0][4 * s + g][q], acc);
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const T l = (T)acc[v];
@@ -237,7 +273,7 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       for (int pb = 0; pb < NPB; ++pb) {
         acc_t acc = zero_acc<E>();
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc = E::mma(fG1[((pb * MB + w) * 4 + s) * 64 + lane], (frag_t)gam[0][s], acc);
+        for (int s = 0; s < 4; ++s) acc = E::mma(g1f[pb][s], (frag_t)gam[0][s], acc);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int pr = 16 * pb + E::row(g, v);
@@ -249,13 +285,14 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       T J[P][4];  // dy_k/dK_m, own rows of the current layer
       double pp[4];
       // pair t (column-major) of layer k: sum over the wave's rows, flushed
-      // every four pairs into outp at the packed positions of those pairs
-      auto pair_sum = [&](auto TI, const T (&gm)[4]) {
+      // every four pairs into outp at the packed positions of those pairs;
+      // gJm = gamma_k (.) J[:, m] of the column m just formed
+      auto pair_sum = [&](auto TI, const T (&gJm)[4]) {
         constexpr int t = decltype(TI)::value;
-        constexpr int m = colmaj_m(t), nn = colmaj_n(t);
+        constexpr int nn = colmaj_n(t);
         T x = (T)0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) x += gm[v] * J[nn][v] * J[m][v];
+        for (int v = 0; v < 4; ++v) x += J[nn][v] * gJm[v];
         pp[t % 4] = (double)x;
         if constexpr (t % 4 == 3 || t == P2 - 1) {
           constexpr int c0 = t - t % 4;
@@ -286,8 +323,11 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
             acc_t acc = jac_product(0, src);
 #pragma unroll
             for (int v = 0; v < 4; ++v) J[m][v] = (T)acc[v] + Bs[0][m][16 * w + E::row(g, v)];
+            T gJm[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) gJm[v] = gam[1][v] * J[m][v];
             static_for<m + 1>([&](auto NI) {
-              pair_sum(std::integral_constant<int, m * (m + 1) / 2 + decltype(NI)::value>{}, gam[1]);
+              pair_sum(std::integral_constant<int, m * (m + 1) / 2 + decltype(NI)::value>{}, gJm);
             });
           });
         } else {
@@ -319,10 +359,14 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
             // Gram pairs of the columns just formed (their partners n <= m are ready)
             static_for<CH>([&](auto JI) {
               constexpr int m = c0 + decltype(JI)::value;
-              if constexpr (m < P)
+              if constexpr (m < P) {
+                T gJm[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) gJm[v] = gam[k - 1][v] * J[m][v];
                 static_for<m + 1>([&](auto NI) {
-                  pair_sum(std::integral_constant<int, m * (m + 1) / 2 + decltype(NI)::value>{}, gam[k - 1]);
+                  pair_sum(std::integral_constant<int, m * (m + 1) / 2 + decltype(NI)::value>{}, gJm);
                 });
+              }
             });
           });
         }
@@ -338,24 +382,30 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
       double v = 0.0;
 #pragma unroll
       for (int ww = 0; ww < NW; ++ww) v += outp[ww][c][qq];
-      if (c == 0) {
-        for (int m = 0; m < P; ++m) v += d_b[m] * Kin[(int64_t)m * n + pt];
-      } else if (c <= P) {
-        v += d_b[c - 1];
-      }
+      if (c >= 1 && c <= P) v += bs[c - 1];
       out[(int64_t)c * n + pt] = v;
     }
     __syncthreads();  // outp, l1buf and xbuf free for the next tile
   };
   if constexpr (!PERSIST) {
-    tile_body(blockIdx.x);  // one tile per workgroup (see the launcher)
+    double kc[S1];  // one tile per workgroup (see the launcher)
+    load_k(blockIdx.x, kc);
+    tile_body(blockIdx.x, kc);
   } else {
     // block-uniform tile loop: every wave of a workgroup runs the same
-    // tiles, so the barriers inside tile_body match
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // tiles, so the barriers inside tile_body match; the next tile's inputs
+    // are in flight while the current one is computed
+    double kn[S1];
+    int64_t tile = blockIdx.x;
+    if (tile < ntiles) load_k(tile, kn);
+    for (; tile < ntiles; tile += gridDim.x) {
       // with the Hessian, nothing read in the tile body stays live across tiles
       if constexpr (HESS) asm volatile("" ::: "memory");
-      tile_body(tile);
+      double kc[S1];
+#pragma unroll
+      for (int s = 0; s < S1; ++s) kc[s] = kn[s];
+      if (tile + gridDim.x < ntiles) load_k(tile + gridDim.x, kn);
+      tile_body(tile, kc);
     }
   }
 }
