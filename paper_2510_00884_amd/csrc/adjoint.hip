@@ -91,14 +91,21 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
   const typename E::frag* fB = frag_ptr<E>(prep, lay, 2);
   const typename E::frag* fAT = (const typename E::frag*)(prep + (dbl ? lay.x_AT : lay.y_AT));
 
-  // weights in registers
-  typename E::frag AV[L - 1][SH], BV[L - 1][S1], AT[L - 1][SH], W1f[MB][S1];
+  // weights in registers; in FP64 the transposed ones in LDS (registers
+  // would spill), shared by the workgroup
+  constexpr bool ATL = PR == PREC_F64 && L * H <= 3 * 64;
+  __shared__ typename E::frag lAT[ATL ? (L - 1) * MB * SH * 64 : 1];
+  __shared__ T cb[L * H];  // hidden biases
+  if constexpr (ATL)
+    for (int i = tid; i < (L - 1) * MB * SH * 64; i += 64 * NW) lAT[i] = fAT[MB * SH * 64 + i];
+  for (int i = tid; i < L * H; i += 64 * NW) cb[i] = t_c[i];
+  typename E::frag AV[L - 1][SH], BV[L - 1][S1], AT[ATL ? 1 : L - 1][ATL ? 1 : SH], W1f[MB][S1];
 #pragma unroll
   for (int k = 2; k <= L; ++k) {
 #pragma unroll
     for (int s = 0; s < SH; ++s) {
       AV[k - 2][s] = fA[(((k - 1) * MB + w) * SH + s) * 64 + lane];
-      AT[k - 2][s] = fAT[(((k - 1) * MB + w) * SH + s) * 64 + lane];
+      if constexpr (!ATL) AT[k - 2][s] = fAT[(((k - 1) * MB + w) * SH + s) * 64 + lane];
     }
 #pragma unroll
     for (int s = 0; s < S1; ++s) BV[k - 2][s] = fB[(((k - 1) * MB + w) * S1 + s) * 64 + lane];
@@ -134,11 +141,22 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
   auto ufrag = [&](int p, int s) -> typename E::frag { return (typename E::frag)us[w][p][lane & 15][4 * s + g]; };
 
   __shared__ SpTab sp[1];
-  if constexpr (std::is_same<T, double>::value) {
-    softplus_tab_fill(sp[0], tid, 64 * NW);
-    __syncthreads();
-  }
+  if constexpr (std::is_same<T, double>::value) softplus_tab_fill(sp[0], tid, 64 * NW);
+  __syncthreads();  // lAT, cb, sp
   const int64_t ntiles = (n + 15) / 16;
+  // this lane's inputs and cotangents of a tile (feature 4 s + g of point q),
+  // the next tile's in flight while the current one is computed
+  auto load_kl = [&](int64_t tile, double (&kv)[S1], double (&lv)[S1]) {
+    const int64_t qq = tile * 16 + q;
+#pragma unroll
+    for (int s = 0; s < S1; ++s) {
+      const int m = 4 * s + g;
+      kv[s] = (qq < n && m < P) ? Kin[(int64_t)m * n + qq] : 0.0;
+      lv[s] = (qq < n && m < P) ? Lam[(int64_t)m * n + qq] : 0.0;
+    }
+  };
+  double kn[S1], ln[S1];
+  if ((int64_t)blockIdx.x < ntiles) load_kl(blockIdx.x, kn, ln);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t base = tile * 16;
     const int64_t qp = base + q;
@@ -146,11 +164,11 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
     typename E::frag kB[S1], lB[S1];
 #pragma unroll
     for (int s = 0; s < S1; ++s) {
-      const int m = 4 * s + g;
-      kB[s] = (valid && m < P) ? (T)Kin[(int64_t)m * n + qp] : (T)0;
-      lB[s] = (valid && m < P) ? (T)Lam[(int64_t)m * n + qp] : (T)0;
+      kB[s] = (T)kn[s];
+      lB[s] = (T)ln[s];
       bacc[s] += (T)lB[s];
     }
+    if (tile + gridDim.x < ntiles) load_kl(tile + gridDim.x, kn, ln);
     if (w == 0) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -168,7 +186,7 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * mb + E::row(g, v);
         T f, f1, f2;
-        softplus3((T)(ay[v] + t_c[r]), f, f1, f2, sp[0]);
+        softplus3((T)(ay[v] + cb[r]), f, f1, f2, sp[0]);
         z1[mb][v] = f; s1[mb][v] = f1; t1[mb][v] = f2;
         yd1[mb][v] = (T)ad[v];
         zd1[mb][v] = f1 * (T)ad[v];
@@ -205,7 +223,7 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * w + E::row(g, v);
         T f, f1, f2;
-        softplus3((T)(ay[v] + t_c[(k - 1) * H + r]), f, f1, f2, sp[0]);
+        softplus3((T)(ay[v] + cb[(k - 1) * H + r]), f, f1, f2, sp[0]);
         sk[k - 2][v] = f1; tk[k - 2][v] = f2; ydk[k - 2][v] = (T)ad[v];
         const T zd = f1 * (T)ad[v];
         if constexpr (k < L) {
@@ -262,8 +280,11 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
       acc_t pd = zero_acc<E>(), pz = zero_acc<E>();
 #pragma unroll
       for (int s = 0; s < SH; ++s) {
-        pd = E::mma(AT[k - 2][s], (typename E::frag)xr[0][4 * s + g][q], pd);
-        pz = E::mma(AT[k - 2][s], (typename E::frag)xr[1][4 * s + g][q], pz);
+        typename E::frag at;
+        if constexpr (ATL) at = lAT[(((k - 2) * MB + w) * SH + s) * 64 + lane];
+        else at = AT[k - 2][s];
+        pd = E::mma(at, (typename E::frag)xr[0][4 * s + g][q], pd);
+        pz = E::mma(at, (typename E::frag)xr[1][4 * s + g][q], pz);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) { zdbar[v] = (T)pd[v]; zbar[v] = (T)pz[v]; }
