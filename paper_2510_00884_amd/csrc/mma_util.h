@@ -163,4 +163,41 @@ __device__ inline double sum16(double x) {
   return x;
 }
 
+// Persistent launch: as many workgroups as fit on the device at once (so the
+// per-workgroup set-up is paid once per resident group), never more than the
+// number of 16-point tiles.
+template <class K>
+static unsigned persistent_grid(K kernel, int block, int64_t ntiles) {
+  static thread_local int cached_dev = -1, cached_cap = 0;
+  static thread_local const void* cached_k = nullptr;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (cached_k != (const void*)kernel || cached_dev != dev) {
+    int cus = 0, per_cu = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
+    cached_cap = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
+    cached_k = (const void*)kernel;
+    cached_dev = dev;
+  }
+  return (unsigned)(ntiles < cached_cap ? ntiles : cached_cap);
+}
+
+// Workgroups of a kernel that fit on one CU at once (cached per kernel and device).
+template <class K>
+static int blocks_per_cu(K kernel, int block) {
+  static thread_local const void* cached_k = nullptr;
+  static thread_local int cached_dev = -1, cached = 0;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (cached_k != (const void*)kernel || cached_dev != dev) {
+    int per_cu = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
+    cached = per_cu;
+    cached_k = (const void*)kernel;
+    cached_dev = dev;
+  }
+  return cached;
+}
+
 }  // namespace pa
