@@ -528,6 +528,46 @@ def bench_batch(args):
                         "(outputs bitwise independent of the batch)", "n_points": n, "batches": res}
 
 
+def pipe_probe(blocks=1024, iters=2000, reps=3):
+    """Do the matrix cores and the vector ALUs of one SIMD run concurrently?
+    Times kinds of work alone in waves 0-3 of 8-wave workgroups, and pairs of
+    kinds split over waves 0-3 and 4-7 (two waves per SIMD); a pair taking
+    the sum of its parts rather than the larger one means they do not
+    overlap."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2510_00884_amd import _lib as L
+    lib = L.load()
+    out = torch.empty(blocks * 512, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    names = {1: "fp64_mfma", 2: "fp32_mfma", 3: "fp64_fma", 4: "fp32_fma", 5: "int_mad"}
+
+    ptr, sp = C.c_void_p(out.data_ptr()), C.c_void_p(stream.cuda_stream)
+
+    def run(lo, hi):
+        L.check(lib.pa_pipe_probe(lo, hi, iters, blocks, ptr, sp), "pa_pipe_probe")  # warm-up launch
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            L.check(lib.pa_pipe_probe(lo, hi, iters, blocks, ptr, sp), "pa_pipe_probe")
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    alone = {names[k]: run(k, 0) for k in names}
+    pairs = {}
+    for lo, hi in ((1, 3), (2, 4), (1, 4), (2, 3), (1, 5), (2, 5)):
+        t = run(lo, hi)
+        a, b = alone[names[lo]], alone[names[hi]]
+        pairs[f"{names[lo]}+{names[hi]}"] = {"ms": t, "sum_ms": a + b, "max_ms": max(a, b),
+                                             "overlap": (a + b - t) / min(a, b)}
+    return {"probe": "pipe_overlap", "blocks": blocks, "waves_per_block": 8, "iters": iters, "alone_ms": alone,
+            "pairs": pairs, "note": "overlap = (sum - pair) / smaller part: 0 = run in turn, 1 = fully concurrent"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -541,6 +581,8 @@ def main():
     ap.add_argument("--cpu-elements", type=int, default=2048,
                     help="headline-mesh elements per process in the oracle CPU baseline (0: skip the baseline)")
     ap.add_argument("--cpu-points", type=int, default=16384, help="points per process in the oracle point sample")
+    ap.add_argument("--pipe-probe", action="store_true",
+                    help="only time the matrix-core / vector-ALU overlap probe (pa_pipe_probe) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -576,6 +618,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.pipe_probe:
+        print(json.dumps(pipe_probe()), flush=True)
+        return
     if args.copy_probe:
         nb = args.copy_probe << 20
         x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")

@@ -404,6 +404,20 @@ int     pa_profile_enable(int32_t on);
 int32_t pa_profile_count(void);
 int     pa_profile_get(int32_t i, const char** name, double* total_ms, int64_t* launches);
 
+/* Measurement utility (not part of the method): one launch of `blocks`
+ * workgroups of eight waves in which waves 0-3 run work of kind kind_lo and
+ * waves 4-7 work of kind kind_hi, each as independent dependency chains of
+ * `iters` steps: 0 none, 1 FP64 16x16x4 matrix-core products (four chains),
+ * 2 FP32 16x16x4 matrix-core products (four chains, twice the steps),
+ * 3 FP64 fused multiply-adds (eight chains, four times the steps), 4 FP32
+ * fused multiply-adds (likewise), 5 32-bit integer multiply-adds (likewise).
+ * Timing pairs of kinds against each kind alone shows whether the two
+ * pipes of one SIMD run concurrently.  out: device buffer of blocks * 512
+ * doubles (written, one value per thread).  Kinds outside 0..5, iters
+ * outside 1..2^20, blocks outside 1..65536 or a NULL out return PA_ERR_ARG
+ * before any launch. */
+int pa_pipe_probe(int32_t kind_lo, int32_t kind_hi, int32_t iters, int32_t blocks, double* out, void* stream);
+
 /* ---------------------------------------------------------------- misc */
 const char* pa_status_string(int status);
 /* Message describing the last PA_ERR_* returned on this thread. */

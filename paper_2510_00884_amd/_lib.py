@@ -86,6 +86,7 @@ SIGNATURES = {
                                           P]),
     "pa_param_backward_workspace": (SZ, [PDESC, C.c_int, I64]),
     "pa_param_backward": (C.c_int, [PDESC, P, C.c_int, I64, P, P, P, P, SZ, P]),
+    "pa_pipe_probe": (C.c_int, [I32, I32, I32, I32, P, P]),
     "pa_profile_enable": (C.c_int, [I32]),
     "pa_profile_count": (I32, []),
     "pa_profile_get": (C.c_int, [I32, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.POINTER(I64)]),

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libpa.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["mlp_adj_h64.hip", "mlp_adj_h32.hip", "mlp_fwd_h64.hip", "mlp_adj_h16.hip", "mlp_fwd_h32.hip",
-           "mlp_fwd_h16.hip", "mlp_valu.hip", "mlp.hip", "adjoint.hip", "kin_chain.hip", "fe.hip", "closed.hip", "api.cpp", "host_setup.cpp"]
+           "mlp_fwd_h16.hip", "mlp_valu.hip", "mlp.hip", "adjoint.hip", "kin_chain.hip", "fe.hip", "closed.hip", "probe.hip", "api.cpp", "host_setup.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", CSRC, "-I", INCLUDE,
           "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -729,6 +729,16 @@ int pa_param_backward(const pa_model_desc* d, const void* prepared, int prec, in
   return hip_check("pa_param_backward");
 }
 
+int pa_pipe_probe(int32_t kind_lo, int32_t kind_hi, int32_t iters, int32_t blocks, double* out, void* stream) {
+  if (kind_lo < 0 || kind_lo > 5 || kind_hi < 0 || kind_hi > 5)
+    return fail(PA_ERR_ARG, "probe kinds must lie in 0..5 (got %d, %d)", kind_lo, kind_hi);
+  if (iters <= 0 || iters > (1 << 20)) return fail(PA_ERR_ARG, "iters must lie in 1..2^20 (got %d)", iters);
+  if (blocks <= 0 || blocks > 65536) return fail(PA_ERR_ARG, "blocks must lie in 1..65536 (got %d)", blocks);
+  if (!out) return fail(PA_ERR_ARG, "out must be non-NULL");
+  launch_pipe_probe(kind_lo, kind_hi, iters, blocks, out, S(stream));
+  return hip_check("pa_pipe_probe");
+}
+
 int pa_profile_enable(int32_t on) {
   g_prof = on != 0;
   if (g_prof) {

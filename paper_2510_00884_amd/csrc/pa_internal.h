@@ -90,6 +90,7 @@ int launch_invariants(int nsv, int64_t n, const double* F, const ModelConst& mc,
 // n points of a batch of a longer call; K and Nout are [..][n].
 int launch_features(int nsv, int64_t n, int64_t ld, const double* F, const ModelConst& mc, double* K,
                     int32_t* n_bad, hipStream_t s);
+int launch_pipe_probe(int kind_lo, int kind_hi, int iters, int blocks, double* out, hipStream_t s);
 int launch_material_cc(int nsv, int64_t n, const double* F, const double* Nout, const ModelConst& mc,
                        double* SC, hipStream_t s);
 int launch_chain_voigt(int nsv, int64_t n, int64_t ld, const double* F, const double* Nout, const double* N0,

@@ -235,3 +235,14 @@ def test_batched_call_arguments_checked_before_launch(lib):
     assert rc == L.PA_ERR_WORKSPACE
     assert lib.pa_energy_stress_tangent_batched(C.byref(d), C.c_void_p(8), 0, 0, 1000, None, None, None, None,
                                                None, None, 0, None) == L.PA_OK
+
+
+def test_pipe_probe_rejects_bad_arguments(lib):
+    """The measurement probe checks its arguments on the host (no launch)."""
+    out = C.c_void_p(0)
+    assert lib.pa_pipe_probe(6, 0, 10, 1, C.c_void_p(1), None) == L.PA_ERR_ARG
+    assert lib.pa_pipe_probe(1, -1, 10, 1, C.c_void_p(1), None) == L.PA_ERR_ARG
+    assert lib.pa_pipe_probe(1, 0, 0, 1, C.c_void_p(1), None) == L.PA_ERR_ARG
+    assert lib.pa_pipe_probe(1, 0, 10, 0, C.c_void_p(1), None) == L.PA_ERR_ARG
+    assert lib.pa_pipe_probe(1, 0, 10, 70000, C.c_void_p(1), None) == L.PA_ERR_ARG
+    assert lib.pa_pipe_probe(1, 0, 10, 1, out, None) == L.PA_ERR_ARG
