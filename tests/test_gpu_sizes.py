@@ -170,3 +170,29 @@ def test_stress_only_sizes(n_sv, h, L, prec):
     e = (rel(psi, ref["psi"]), rel(P, ref["P"]))
     say("  errors psi/P", e)
     assert max(e) < tol
+
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 2e-2, "bf16_corr": 2e-2}
+
+
+@pytest.mark.parametrize("n", [1, 17])
+@pytest.mark.parametrize("h,L", [(32, 2), (64, 3)])
+@pytest.mark.parametrize("algorithm", ["adjoint", "forward"])
+def test_tiny_batches_every_precision(n, h, L, algorithm):
+    """One point, and one full tile plus one: every network kernel (persistent
+    grids of a single workgroup, waves with no tile) at every precision, with
+    and without the tangent, against the oracle at the precision's tolerance
+    (BF16 + correction: P at the FP32 tolerance)."""
+    api = need_gpu()
+    gm, om, *_ = build(api, 2, h, L, algorithm=algorithm)
+    F = synth.sample_F(n, seed=21)
+    ref = ncm.stress_stiffness(F, om)
+    Ft = torch.tensor(F, device="cuda")
+    for prec, tol in TOL.items():
+        say("tiny batch", algorithm, prec, n, h, L)
+        psi, P, A = unpack(api.energy_stress_tangent(gm, Ft, prec=prec), n)
+        ptol = 1e-5 if prec == "bf16_corr" else tol
+        assert rel(P, ref["P"]) < ptol and rel(A, ref["A"]) < tol
+        out = api.energy_stress_tangent(gm, Ft, prec=prec, A=False)
+        P2 = out["P"].cpu().numpy().T.reshape(n, 3, 3)
+        assert rel(P2, ref["P"]) < ptol
