@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(256) k_adj_inputs(int64_t n, const double* __r
 }
 
 template <int H, int L, int P, int PR>
-__global__ void __launch_bounds__(64 * (H / 16))
+__global__ void __launch_bounds__(64 * (H / 16)) __attribute__((amdgpu_waves_per_eu(PR == PREC_F32 ? 2 : 1)))
 k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout tl, int64_t n,
             const double* __restrict__ Kin, const double* __restrict__ Lam, double* __restrict__ part) {
   using E = typename std::conditional<PR == PREC_F64, EngF64, EngF32>::type;
@@ -91,15 +91,19 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
   const typename E::frag* fB = frag_ptr<E>(prep, lay, 2);
   const typename E::frag* fAT = (const typename E::frag*)(prep + (dbl ? lay.x_AT : lay.y_AT));
 
-  // weights in registers; in FP64 the transposed ones in LDS (registers
-  // would spill), shared by the workgroup
-  constexpr bool ATL = PR == PREC_F64 && L * H <= 3 * 64;
+  // this wave's forward fragments in registers; the transposed ones and the
+  // layer-1 fragments in LDS, shared by the workgroup (in FP64 registers
+  // would spill; in FP32 the smaller register budget lets two workgroups
+  // share a compute unit)
+  constexpr bool ATL = PR == PREC_F32 || L * H <= 3 * 64;
   __shared__ typename E::frag lAT[ATL ? (L - 1) * MB * SH * 64 : 1];
+  __shared__ typename E::frag lW1f[MB * S1 * 64];
   __shared__ T cb[L * H];  // hidden biases
   if constexpr (ATL)
     for (int i = tid; i < (L - 1) * MB * SH * 64; i += 64 * NW) lAT[i] = fAT[MB * SH * 64 + i];
+  for (int i = tid; i < MB * S1 * 64; i += 64 * NW) lW1f[i] = fW1[i];
   for (int i = tid; i < L * H; i += 64 * NW) cb[i] = t_c[i];
-  typename E::frag AV[L - 1][SH], BV[L - 1][S1], AT[ATL ? 1 : L - 1][ATL ? 1 : SH], W1f[MB][S1];
+  typename E::frag AV[L - 1][SH], BV[L - 1][S1], AT[ATL ? 1 : L - 1][ATL ? 1 : SH];
 #pragma unroll
   for (int k = 2; k <= L; ++k) {
 #pragma unroll
@@ -110,10 +114,6 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
 #pragma unroll
     for (int s = 0; s < S1; ++s) BV[k - 2][s] = fB[(((k - 1) * MB + w) * S1 + s) * 64 + lane];
   }
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int s = 0; s < S1; ++s) W1f[mb][s] = fW1[(mb * S1 + s) * 64 + lane];
   T a_own[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) a_own[v] = t_a[16 * w + E::row(g, v)];
@@ -176,26 +176,40 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
         kl[1][4 * s + g][q] = s < S1 ? (T)lB[s < S1 ? s : 0] : (T)0;
       }
     }
-    // ---------------- forward: layer 1 (all rows), primal and tangent
-    T z1[MB][4], zd1[MB][4], s1[MB][4], t1[MB][4], yd1[MB][4];
+    // ---------------- forward: layer 1 (all rows), primal and tangent; the
+    // reverse sweep needs F', F'' and the tangent of this wave's rows only
+    T z1[MB][4], zd1[MB][4], s1w[4], t1w[4], yd1w[4];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-      acc_t ay = mma_in<E, P>(W1f[mb], kB, zero_acc<E>());
-      acc_t ad = mma_in<E, P>(W1f[mb], lB, zero_acc<E>());
+      typename E::frag a1[S1];
+#pragma unroll
+      for (int s = 0; s < S1; ++s) a1[s] = lW1f[(mb * S1 + s) * 64 + lane];
+      acc_t ay = mma_in<E, P>(a1, kB, zero_acc<E>());
+      acc_t ad = mma_in<E, P>(a1, lB, zero_acc<E>());
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * mb + E::row(g, v);
         T f, f1, f2;
         softplus3((T)(ay[v] + cb[r]), f, f1, f2, sp[0]);
-        z1[mb][v] = f; s1[mb][v] = f1; t1[mb][v] = f2;
-        yd1[mb][v] = (T)ad[v];
+        z1[mb][v] = f;
         zd1[mb][v] = f1 * (T)ad[v];
+        if (mb == w) {  // wave-uniform
+          s1w[v] = f1;
+          t1w[v] = f2;
+          yd1w[v] = (T)ad[v];
+        }
       }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      zs[0][0][16 * w + E::row(g, v)][q] = z1[w][v];
-      zs[0][1][16 * w + E::row(g, v)][q] = zd1[w][v];
+      T zo = z1[0][v], zdo = zd1[0][v];
+#pragma unroll
+      for (int mb = 1; mb < MB; ++mb) {
+        zo = (mb == w) ? z1[mb][v] : zo;
+        zdo = (mb == w) ? zd1[mb][v] : zdo;
+      }
+      zs[0][0][16 * w + E::row(g, v)][q] = zo;
+      zs[0][1][16 * w + E::row(g, v)][q] = zdo;
     }
     // ---------------- forward: layers 2..L (own rows)
     T sk[L - 1][4], tk[L - 1][4], ydk[L - 1][4];
@@ -295,8 +309,8 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
       T ydb[4], yb[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        ydb[v] = zdbar[v] * s1[w][v];
-        yb[v] = zbar[v] * s1[w][v] + zdbar[v] * yd1[w][v] * t1[w][v];
+        ydb[v] = zdbar[v] * s1w[v];
+        yb[v] = zbar[v] * s1w[v] + zdbar[v] * yd1w[v] * t1w[v];
         cacc[0][v] += yb[v];
         const int rl = E::row(g, v);
         us[w][0][rl][q] = ydb[v];
