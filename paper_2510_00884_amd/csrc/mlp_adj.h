@@ -96,7 +96,7 @@ k_mlp_adj(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
   // this wave's layer-1 Gram and reverse-product fragments, the same for
   // every tile, held in registers where the budget allows (no L2 latency in
   // the tile loop)
-  constexpr bool HAT = HESS && (L - 1) * SH <= 32;
+  constexpr bool HAT = (L - 1) * SH <= 32;
   frag_t g1f[HESS ? NPB : 1][4], atf[HAT ? L - 1 : 1][HAT ? SH : 1];
   if constexpr (HESS) {
 #pragma unroll
