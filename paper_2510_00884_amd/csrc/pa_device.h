@@ -77,18 +77,12 @@ __device__ inline double div_unit(double a, double d) {
   const double q = a * r;
   return fma(fma(-d, q, a), r, q);
 }
-__device__ inline float div_unit(float a, float d) {
-  float r = __builtin_amdgcn_rcpf(d);
-  r = fmaf(fmaf(-d, r, 1.0f), r, r);
-  const float q = a * r;
-  return fmaf(fmaf(-d, q, a), r, q);
-}
 
 // log(1 + x) for x in [0, 1] (here x = e^{-|y|}).  For x above sqrt(2) - 1,
 // log(1 + x) = ln 2 + log(1 + g) with g = (x - 1)/2 in (-0.293, 0]; then
 // log(1 + g) = 2 atanh(s), s = g / (2 + g), |s| <= 0.1716, summed as the odd
-// series 2 s sum_k s^{2k} / (2k + 1).  Terms to k = 9 (FP64) or k = 4 (FP32)
-// leave a truncation below half an ulp.
+// series 2 s sum_k s^{2k} / (2k + 1).  Terms to k = 9 leave a truncation
+// below half an ulp.
 __device__ inline double log1p_unit(double x) {
   const bool hi = x > 0.41421356237309503;
   const double g = hi ? 0.5 * (x - 1.0) : x;
@@ -107,19 +101,6 @@ __device__ inline double log1p_unit(double x) {
   const double r = fma(t * s2, p, t);
   return hi ? 0.6931471805599453 + r : r;
 }
-__device__ inline float log1p_unit(float x) {
-  const bool hi = x > 0.41421356f;
-  const float g = hi ? 0.5f * (x - 1.0f) : x;
-  const float s = div_unit(g, 2.0f + g);
-  const float s2 = s * s;
-  float p = 1.0f / 9.0f;
-  p = fmaf(p, s2, 1.0f / 7.0f);
-  p = fmaf(p, s2, 1.0f / 5.0f);
-  p = fmaf(p, s2, 1.0f / 3.0f);
-  const float t = 2.0f * s;
-  const float r = fmaf(t * s2, p, t);
-  return hi ? 0.69314718f + r : r;
-}
 
 __device__ inline void softplus3(double y, double& f, double& f1, double& f2) {
   const double e = exp(-fabs(y));
@@ -128,10 +109,27 @@ __device__ inline void softplus3(double y, double& f, double& f1, double& f2) {
   f1 = (y >= 0.0) ? r : e * r;
   f2 = e * r * r;
 }
+// FP32 on the hardware base-2 exponential and logarithm (each within about
+// two units of 2^-24 relative, checked on gfx950 over their whole range here,
+// the logarithm also just above 1):
+//   e^{-t} = 2^a 2^da with a = -t log2 e rounded, da its rounding error (one
+//   fused multiply-add) plus t times the low part of log2 e, applied to first
+//   order (|da| < 1e-5 for t < 128, where e^{-t} still has FP32 digits);
+//   log(1 + e) = log(u) + (1 + e - u)/u for the rounded u = 1 + e, whose
+//   rounding error 1 + e - u = e - (u - 1) is exact.
+// Measured against FP64 over |y| <= 110: F within 3.6, F' within 4.0 and F''
+// within 6.1 units of 2^-24 relative.  y = NaN gives NaN outputs.
 __device__ inline void softplus3(float y, float& f, float& f1, float& f2) {
-  const float e = expf(-fabsf(y));
-  const float r = div_unit(1.0f, 1.0f + e);
-  f = fmaxf(y, 0.0f) + log1p_unit(e);
+  const float t = fabsf(y);
+  const float a = -t * 1.44269502f;
+  float da = fmaf(-t, 1.44269502f, -a) - t * 1.925963e-8f;
+  da = (t < 128.0f) ? da : 0.0f;  // infinite t: e = 0 without a NaN correction
+  const float p = __builtin_amdgcn_exp2f(a);
+  const float e = fmaf(p * da, 0.693147182f, p);
+  const float u = 1.0f + e;
+  float r = __builtin_amdgcn_rcpf(u);
+  r = fmaf(fmaf(-u, r, 1.0f), r, r);
+  f = fmaxf(y, 0.0f) + fmaf(__builtin_amdgcn_logf(u), 0.693147182f, (e - (u - 1.0f)) * r);
   f1 = (y >= 0.0f) ? r : e * r;
   f2 = e * r * r;
 }
