@@ -319,16 +319,7 @@ def test_closed_inner_functions(kind, n_sv, normalize):
     close(cc, ref["cc"], 1e-12, "cc")
 
 
-@pytest.mark.parametrize("algorithm", ["adjoint", "forward"])
-@pytest.mark.parametrize("n_sv,h,L", [(2, 32, 2), (2, 64, 3)])
-def test_large_preactivations_fp64(algorithm, n_sv, h, L):
-    """Hidden biases ~ N(0, 300), so the pre-activations of every layer span
-    hundreds in both signs: the softplus and its derivatives at their far
-    tails (e^{-|y|} down to underflow, F ~ y, F' ~ 0 or 1, F'' ~ 0), in the
-    kernels' own softplus (tabled in the adjoint form), against the oracle's
-    max(y, 0) + log1p(e^{-|y|}) at 1e-12."""
-    api = need_gpu()
-    say("large pre-activations", algorithm, n_sv, h, L)
+def _large_bias_model(api, n_sv, h, L, algorithm):
     p = synth.num_inputs(n_sv)
     theta = synth.micnn_params(p, h, L, seed=3)
     r = np.random.default_rng(7)
@@ -342,6 +333,49 @@ def test_large_preactivations_fp64(algorithm, n_sv, h, L):
     Av = synth.structural_vectors(n_sv)
     gm = api.Model(theta, n_sv, h, L, A=Av, normalize=True, algorithm=algorithm)
     om = ncm.model_from_theta(theta, p, h, L, Av, normalize=True)
+    return gm, om
+
+
+@pytest.mark.parametrize("algorithm", ["adjoint", "forward"])
+@pytest.mark.parametrize("n_sv,h,L", [(2, 32, 2), (2, 64, 3)])
+def test_large_preactivations_fp32(algorithm, n_sv, h, L):
+    """The FP32 softplus (hardware exponential and logarithm) at its far
+    tails: pre-activations spanning hundreds in both signs, where e^{-|y|}
+    underflows in FP32.  Outputs are finite, P and AA match the oracle at the
+    FP32 tolerance of the other material tests.  Psi is the difference
+    N(K) - N(0) - kappa . K of terms in the thousands here, so its FP32
+    rounding is bounded relative to those terms, not to Psi: the error is
+    measured against the norm of |N(K)| + |N(0)| + |kappa . K|."""
+    api = need_gpu()
+    say("large pre-activations fp32", algorithm, n_sv, h, L)
+    gm, om = _large_bias_model(api, n_sv, h, L, algorithm)
+    n = 1003
+    F = synth.sample_F(n, seed=8)
+    psi, P, A = unpack(api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec="fp32"), n)
+    assert np.isfinite(psi).all() and np.isfinite(P).all() and np.isfinite(A).all()
+    ref = ncm.stress_stiffness(F, om)
+    K = ref["K"]
+    npair = om.kappa.shape[0]
+    terms = (np.abs(ncm.micnn_value(K, om.hidden, om.a, om.b)) + abs(om.N0)
+             + np.abs(K[:, 3:3 + npair] @ om.kappa))
+    e_psi = np.linalg.norm(psi - ref["psi"]) / np.linalg.norm(terms)
+    say("  psi error against its terms", f"{e_psi:.1e}", "(against psi itself", f"{rel(psi, ref['psi']):.1e})")
+    assert e_psi < 1e-5, e_psi
+    close(P, ref["P"], 1e-5, "P")
+    close(A, ref["A"], 1e-5, "A")
+
+
+@pytest.mark.parametrize("algorithm", ["adjoint", "forward"])
+@pytest.mark.parametrize("n_sv,h,L", [(2, 32, 2), (2, 64, 3)])
+def test_large_preactivations_fp64(algorithm, n_sv, h, L):
+    """Hidden biases ~ N(0, 300), so the pre-activations of every layer span
+    hundreds in both signs: the softplus and its derivatives at their far
+    tails (e^{-|y|} down to underflow, F ~ y, F' ~ 0 or 1, F'' ~ 0), in the
+    kernels' own softplus (tabled in the adjoint form), against the oracle's
+    max(y, 0) + log1p(e^{-|y|}) at 1e-12."""
+    api = need_gpu()
+    say("large pre-activations", algorithm, n_sv, h, L)
+    gm, om = _large_bias_model(api, n_sv, h, L, algorithm)
     n = 1003
     F = synth.sample_F(n, seed=8)
     psi, P, A = unpack(api.energy_stress_tangent(gm, torch.tensor(F, device="cuda"), prec="fp64"), n)
