@@ -137,11 +137,11 @@ __device__ inline void softplus3(float y, float& f, float& f1, float& f2) {
 // FP64 softplus with two 64-entry tables, for kernels that fill them once
 // per workgroup (in LDS) and evaluate many activations:
 //   e^{-t} = 2^{-N/64} e^{-r},  N = rint(64 t / ln 2),  |r| <= ln 2 / 128,
-// with 2^{-j/64} from the table and e^{-r} from its Taylor polynomial to r^6
-// (first dropped term below 3e-20); the reduction t - N ln2/64 is exact in
-// its first fused step (|r| < 2^-7) and adds the low part of ln2/64 in a
-// second.  With j = floor(64 e) and a reciprocal w_j of the centre of the
-// j-th 64th of [1, 2] (w_0 = 1),
+// with 2^{-j/64} from the table and e^{-r} from its Taylor polynomial to r^5
+// (first dropped term below 4e-17 relative); the reduction t - N ln2/64 is
+// exact in its first fused step (|r| < 2^-7) and adds the low part of ln2/64
+// in a second.  With j = floor(64 e) (0 .. 64, e <= 1) and a reciprocal w_j of
+// the centre of the j-th 64th of [1, 2 + 1/64] (w_0 = 1),
 //   log(1 + e) = -log w_j + log(1 + d),  d = (1 + e) w_j - 1 = e w_j + (w_j - 1),
 // where d comes from one fused multiply-add of exact operands (w_j - 1 is
 // exact), so it is correctly rounded for any stored w_j, and |d| < 1/64;
@@ -149,11 +149,11 @@ __device__ inline void softplus3(float y, float& f, float& f1, float& f2) {
 // F keeps its relative accuracy for large negative y (then j = 0, d = e).
 struct SpTab {
   double e[64];   // 2^{-j/64}
-  double2 l[64];  // {w_j, -log w_j}
+  double2 l[65];  // {w_j, -log w_j}
 };
 __device__ inline void softplus_tab_fill(SpTab& T, int tid, int nthreads) {
-  for (int j = tid; j < 64; j += nthreads) {
-    T.e[j] = exp2(-(double)j / 64.0);
+  for (int j = tid; j < 65; j += nthreads) {
+    if (j < 64) T.e[j] = exp2(-(double)j / 64.0);
     const double w = (j == 0) ? 1.0 : 1.0 / (1.0 + ((double)j + 0.5) / 64.0);
     T.l[j] = make_double2(w, -log(w));
   }
@@ -165,8 +165,7 @@ __device__ inline void softplus3(double y, double& f, double& f1, double& f2, co
   double r = fma(-kd, 0x1.62e42fefa39efp-7, t);
   r = fma(-kd, 0x1.abc9e3b39803fp-62, r);
   const double x = -r;
-  double p = 1.0 / 720.0;
-  p = fma(p, x, 1.0 / 120.0);
+  double p = 1.0 / 120.0;
   p = fma(p, x, 1.0 / 24.0);
   p = fma(p, x, 1.0 / 6.0);
   p = fma(p, x, 0.5);
@@ -177,7 +176,7 @@ __device__ inline void softplus3(double y, double& f, double& f1, double& f2, co
   double rc = __builtin_amdgcn_rcp(u);
   rc = fma(fma(-u, rc, 1.0), rc, rc);
   rc = fma(fma(-u, rc, 1.0), rc, rc);
-  const double2 lw = T.l[min((int)(e * 64.0), 63)];
+  const double2 lw = T.l[(int)(e * 64.0)];
   const double d = fma(e, lw.x, lw.x - 1.0);
   double q = 1.0 / 9.0;
   q = fma(q, d, -0.125);
