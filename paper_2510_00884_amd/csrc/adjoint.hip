@@ -176,61 +176,41 @@ k_param_bwd(const unsigned char* __restrict__ prep, PrepLayout lay, ThetaLayout 
         kl[1][4 * s + g][q] = s < S1 ? (T)lB[s < S1 ? s : 0] : (T)0;
       }
     }
-    // ---------------- forward: layer 1 (all rows), primal and tangent; the
-    // reverse sweep needs F', F'' and the tangent of this wave's rows only
-    T z1[MB][4], zd1[MB][4], s1w[4], t1w[4], yd1w[4];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
+    // ---------------- forward: layer 1, this wave's rows (primal and
+    // tangent), into LDS for the next layer; the reverse sweep keeps F', F''
+    // and the tangent pre-activation
+    T s1w[4], t1w[4], yd1w[4];
+    {
       typename E::frag a1[S1];
 #pragma unroll
-      for (int s = 0; s < S1; ++s) a1[s] = lW1f[(mb * S1 + s) * 64 + lane];
+      for (int s = 0; s < S1; ++s) a1[s] = lW1f[(w * S1 + s) * 64 + lane];
       acc_t ay = mma_in<E, P>(a1, kB, zero_acc<E>());
       acc_t ad = mma_in<E, P>(a1, lB, zero_acc<E>());
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = 16 * mb + E::row(g, v);
+        const int r = 16 * w + E::row(g, v);
         T f, f1, f2;
         softplus3((T)(ay[v] + cb[r]), f, f1, f2, sp[0]);
-        z1[mb][v] = f;
-        zd1[mb][v] = f1 * (T)ad[v];
-        if (mb == w) {  // wave-uniform
-          s1w[v] = f1;
-          t1w[v] = f2;
-          yd1w[v] = (T)ad[v];
-        }
+        s1w[v] = f1;
+        t1w[v] = f2;
+        yd1w[v] = (T)ad[v];
+        zs[0][0][r][q] = f;
+        zs[0][1][r][q] = f1 * (T)ad[v];
       }
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      T zo = z1[0][v], zdo = zd1[0][v];
-#pragma unroll
-      for (int mb = 1; mb < MB; ++mb) {
-        zo = (mb == w) ? z1[mb][v] : zo;
-        zdo = (mb == w) ? zd1[mb][v] : zdo;
-      }
-      zs[0][0][16 * w + E::row(g, v)][q] = zo;
-      zs[0][1][16 * w + E::row(g, v)][q] = zdo;
     }
     // ---------------- forward: layers 2..L (own rows)
     T sk[L - 1][4], tk[L - 1][4], ydk[L - 1][4];
     static_for<L - 1>([&](auto KI) {
       constexpr int k = decltype(KI)::value + 2;
       T zsrc[MB][4], zdsrc[MB][4];
-      if constexpr (k == 2) {
+      __syncthreads();  // every wave's rows of layer k - 1 are in zs
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) { zsrc[mb][v] = z1[mb][v]; zdsrc[mb][v] = zd1[mb][v]; }
-      } else {
-        __syncthreads();
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            zsrc[mb][v] = zs[k - 2][0][16 * mb + E::row(g, v)][q];
-            zdsrc[mb][v] = zs[k - 2][1][16 * mb + E::row(g, v)][q];
-          }
-      }
+        for (int v = 0; v < 4; ++v) {
+          zsrc[mb][v] = zs[k - 2][0][16 * mb + E::row(g, v)][q];
+          zdsrc[mb][v] = zs[k - 2][1][16 * mb + E::row(g, v)][q];
+        }
       acc_t ay = mma_in<E, P>(BV[k - 2], kB, mma_src<E, MB>(AV[k - 2], zsrc, zero_acc<E>()));
       acc_t ad = mma_in<E, P>(BV[k - 2], lB, mma_src<E, MB>(AV[k - 2], zdsrc, zero_acc<E>()));
 #pragma unroll
