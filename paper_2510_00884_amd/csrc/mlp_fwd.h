@@ -72,9 +72,38 @@ k_mlp_fwd(const unsigned char* __restrict__ prep, PrepLayout lay, int64_t n,
     }
   }
 
-  // ---- layer 1, all rows: y1 = W1 K + c1
+  // ---- layer 1: y1 = W1 K + c1.  With three or more hidden layers each
+  // wave evaluates its own rows and the values, F' and F'' of every row come
+  // back through the exchange buffer (free until the value column); with two,
+  // each wave evaluates all rows (the buffer holds one column)
   T s1[MB][4], t1[MB][4], z1[MB][4];
-  {
+  if constexpr (CH >= 3) {
+    const typename EV::frag* fW1 = frag_ptr<EV>(prep, lay, 0);
+    typename EV::frag a1[S1V];
+#pragma unroll
+    for (int s = 0; s < S1V; ++s) a1[s] = fW1[(w * S1V + s) * 64 + lane];
+    typename EV::acc acc = mma_in<EV, P>(a1, kB, zero_acc<EV>());
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * w + EV::row(g, v);
+      T f, f1, f2;
+      softplus3((T)(acc[v] + t_c[r]), f, f1, f2);
+      xbuf[0][r][q] = f;
+      xbuf[1][r][q] = f1;
+      xbuf[2][r][q] = f2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * mb + EV::row(g, v);
+        z1[mb][v] = xbuf[0][r][q];
+        s1[mb][v] = xbuf[1][r][q];
+        t1[mb][v] = xbuf[2][r][q];
+      }
+    __syncthreads();  // xbuf free for the value column
+  } else {
     const typename EV::frag* fW1 = frag_ptr<EV>(prep, lay, 0);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
