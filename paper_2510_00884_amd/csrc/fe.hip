@@ -586,7 +586,7 @@ __global__ void __launch_bounds__(256) k_gather_assemble(
     const double* __restrict__ rw, double* __restrict__ r, double* __restrict__ vals, int max_row) {
   constexpr int ND = 3 * NEN, NB = 3 * ND, R = (NB + 63) / 64;
   constexpr int NS = 9 * sym_blocks<NEN>(), HN = NEN / 2;
-  constexpr int GB = 8;  // elements whose loads are in flight together
+  constexpr int GB = 4;  // elements whose loads are in flight together (measured: 4 beat 8 and 16)
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t node = (int64_t)blockIdx.x * (blockDim.x / 64) + wv;
