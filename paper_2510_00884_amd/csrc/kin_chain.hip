@@ -217,13 +217,14 @@ int launch_chain_voigt(int nsv, int64_t n, int64_t ld, const double* F, const do
   return 0;
 }
 
+// k_chain in workgroups of 128 threads (2^21 points: 0.650 -> 0.614 ms against 256)
 int launch_chain(int nsv, int64_t n, int64_t ld, const double* F, const double* Nout, const double* N0,
                  const ModelConst& mc, double* psi, double* P, double* A, int32_t* n_bad, hipStream_t s) {
   if (n == 0) return 0;
   switch (nsv) {
-    case 0: k_chain<0><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, Nout, N0, mc, psi, P, A, n_bad); break;
-    case 1: k_chain<1><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, Nout, N0, mc, psi, P, A, n_bad); break;
-    case 2: k_chain<2><<<nblk(n, 256), 256, 0, s>>>(n, ld, F, Nout, N0, mc, psi, P, A, n_bad); break;
+    case 0: k_chain<0><<<nblk(n, 128), 128, 0, s>>>(n, ld, F, Nout, N0, mc, psi, P, A, n_bad); break;
+    case 1: k_chain<1><<<nblk(n, 128), 128, 0, s>>>(n, ld, F, Nout, N0, mc, psi, P, A, n_bad); break;
+    case 2: k_chain<2><<<nblk(n, 128), 128, 0, s>>>(n, ld, F, Nout, N0, mc, psi, P, A, n_bad); break;
     default: return -1;
   }
   return 0;
